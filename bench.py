@@ -1,0 +1,236 @@
+"""Benchmark: interval pairs/s and BD actions/s on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch]
+
+One step = the whole hot path on the 2D flat causal diamond with N = 131072
+elements (seed 3): sprinkle + time sort, link (2 GiB packed matrix), interval
+counting (abundances N_0..N_3, R, sum of interior counts) and the BD action,
+all through the C ABI.  Inputs are synthetic (the paper's workloads are
+sprinklings too).  ``value`` = related pairs whose interval size was computed,
+per second of the whole step.
+
+Also reported on the same line:
+  * roofline: the counting kernel (the dominant one), timed with HIP events
+    on the library's stream over the timed region;
+  * cpu_baseline: the CPU oracle's counting rate on a bounded row sample of
+    the same set, on this host's cores;
+  * ensemble: 512 sets (N uniform in [256, 4096], d in {2, 4}) as BD
+    actions/s, batched (one cs_batch_run) vs per-set (a loop of cs_* calls).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = dict(d=2, N=131072, seed=3)
+PEAK = {
+    "int8_mfma_tops": 5.0e15,      # dense int8 MFMA, ops/s
+    "alu_int32_ops": 256 * 64 * 2.4e9,  # 256 CU x 64 lanes x 2.4 GHz, 32-bit VALU ops/s
+    "hbm_bytes": 8.0e12,
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def span_words(bits: np.ndarray, N: int) -> int:
+    """W_alg = sum over related pairs i<j of the number of 64-bit words that
+    hold columns i+1..j-1 (the words Alg. 5 ANDs and counts)."""
+    W = bits.shape[1]
+    tot = 0
+    rowblk = 1024
+    wi = np.arange(W, dtype=np.int64)
+    for lo in range(0, N, rowblk):
+        hi = min(lo + rowblk, N)
+        blk = bits[lo:hi]
+        i = np.arange(lo, hi, dtype=np.int64)[:, None]
+        # keep columns j > i only
+        first = (i + 1) >> 6
+        keep = np.where(wi[None, :] > (i >> 6), np.uint64(0xFFFFFFFFFFFFFFFF), np.uint64(0))
+        same = wi[None, :] == (i >> 6)
+        shift = ((i & 63) + 1).astype(np.uint64)
+        above = np.where(shift >= 64, np.uint64(0), (~np.uint64(0)) << np.minimum(shift, 63).astype(np.uint64))
+        keep = np.where(same, above, keep)
+        x = blk & keep
+        cnt = np.bitwise_count(x).astype(np.int64)
+        # a related j in word w spans words first..(j-1)>>6: (w - first + 1), minus one if j%64 == 0
+        b0 = (x & np.uint64(1)).astype(np.int64)
+        tot += int((cnt * (wi[None, :] - first + 1)).sum() - b0.sum())
+    # adjacent related pairs (j = i+1) span no word; the formula gave them one
+    i = np.arange(N - 1, dtype=np.int64)
+    j = i + 1
+    adj = (bits[i, j >> 6] >> (j & 63).astype(np.uint64)) & np.uint64(1)
+    tot -= int(adj[(j & 63) != 0].sum())
+    return tot
+
+
+def run_step(cs, ctx, ev, path):
+    d, N, seed = WORKLOAD["d"], WORKLOAD["N"], WORKLOAD["seed"]
+    s = cs.cs_sprinkle(ctx, d, N, seed)
+    cs.cs_link(ctx, s)
+    ev[0].record(ev[2])
+    n, R, sm = cs.cs_interval_abundances(ctx, s, 3, path)
+    ev[1].record(ev[2])
+    S = cs.cs_bd_action(ctx, s)
+    return s, n, R, sm, S
+
+
+def cpu_baseline(budget_s: float = 12.0):
+    import oracle
+    d, N, seed = WORKLOAD["d"], WORKLOAD["N"], WORKLOAD["seed"]
+    t0 = time.time()
+    coords, _, _ = oracle.sprinkle(d, N, seed)
+    bits = oracle.link(d, coords)
+    t_link = time.time() - t0
+    nthreads = oracle.num_threads()
+    # evenly spaced 64-row blocks until the time budget is used
+    starts = [int(x) for x in np.linspace(0, N - 64, 64)]
+    order = [starts[k] for k in np.random.default_rng(0).permutation(len(starts))]
+    pairs = 0
+    rows = 0
+    t_count = 0.0
+    for lo in order:
+        t1 = time.time()
+        _, R, _ = oracle.count_bits(bits, N, nbins=4, rows=(lo, lo + 64))
+        t_count += time.time() - t1
+        pairs += R
+        rows += 64
+        if t_count > budget_s:
+            break
+    return {
+        "value": pairs / t_count, "unit": "interval pairs/s", "cores": nthreads, "kind": "oracle",
+        "sample": "%d rows (64-row blocks evenly spread over the N=131072 2D set, seed 3): interval "
+                  "counts of all %d related pairs (i,j) with i in the sample, %.1f s; the oracle's "
+                  "full link (%.1f s) not included" % (rows, pairs, t_count, t_link),
+    }
+
+
+def ensemble(cs, ctx, nsets=512):
+    import causet_inputs as ci
+    plan = ci.ensemble_plan(nsets)
+    out = {}
+    try:
+        cs.cs_batch_run(ctx, plan)  # warm-up (graph capture, tuning)
+        t0 = time.time()
+        res = cs.cs_batch_run(ctx, plan)
+        tb = time.time() - t0
+        out["batched_actions_per_s"] = nsets / tb
+        out["batched_s"] = tb
+    except cs.CsError as e:
+        out["batched_error"] = str(e)
+        res = None
+    t0 = time.time()
+    per = []
+    for (d, N, seed) in plan:
+        s = cs.cs_sprinkle(ctx, d, N, seed)
+        cs.cs_link(ctx, s)
+        n, R, sm = cs.cs_interval_abundances(ctx, s, 3, 0)
+        per.append((list(map(int, n)), R, sm, cs.cs_bd_action(ctx, s)))
+        cs.cs_set_free(s)
+    tp = time.time() - t0
+    out["per_set_actions_per_s"] = nsets / tp
+    out["per_set_s"] = tp
+    if res is not None:
+        out["batched_equals_per_set"] = all(
+            r["n"] == p[0] and r["R"] == p[1] and r["summ"] == p[2] and r["S"] == p[3]
+            for r, p in zip(res, per))
+    out["sets"] = nsets
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--path", type=int, default=1, help="0 auto, 1 popcount, 2 MFMA")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-span", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see the sharding paragraph in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1709_03013_amd as cs
+
+    torch.cuda.init()
+    stream = torch.cuda.Stream(device=0)
+    ctx = cs.cs_create(0, 0, stream.cuda_stream)
+    ev = [torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True), stream]
+
+    for _ in range(a.warmup):
+        s, *_ = run_step(cs, ctx, ev, a.path)
+        cs.cs_set_free(s)
+    torch.cuda.synchronize()
+    count_ms = []
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        s, n, R, sm, S = run_step(cs, ctx, ev, a.path)
+        ev[1].synchronize()
+        count_ms.append(ev[0].elapsed_time(ev[1]))
+        if k + 1 < a.steps:
+            cs.cs_set_free(s)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1000.0 / a.steps
+    log("step %.1f ms, count %s ms" % (ms_step, ["%.1f" % x for x in count_ms]))
+
+    N = WORKLOAD["N"]
+    path_used = a.path if a.path else (2 if N >= 2048 else 1)
+    t_count = float(np.mean(count_ms)) / 1000.0
+    if path_used == 2:
+        ops = 2.0 * math.comb(N, 3)
+        roof = {"bound": "mfma", "achieved": ops / t_count / 1e12, "peak": PEAK["int8_mfma_tops"] / 1e12,
+                "unit": "TFLOP/s", "kernel": "k_count_mfma", "work": "2*C(N,3) int8 ops (one MAC per triple i<k<j)"}
+    else:
+        if a.no_span:
+            walg = None
+        else:
+            bits = cs.cs_get_bitset(ctx, s)
+            walg = span_words(bits, N)
+            del bits
+        ops = 4.0 * walg if walg else float("nan")
+        roof = {"bound": "alu", "achieved": ops / t_count / 1e12, "peak": PEAK["alu_int32_ops"] / 1e12,
+                "unit": "TOP/s", "kernel": "k_count_pop",
+                "work": "4 int32 ops per 64-bit word of the span of every related pair (W_alg=%s)" % walg}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["count_ms"] = float(np.mean(count_ms))
+    cs.cs_set_free(s)
+
+    ens = None if a.no_batch else ensemble(cs, ctx)
+    cpu = None if a.no_cpu else cpu_baseline()
+    cs.cs_destroy(ctx)
+
+    rec = {
+        "metric": "interval pairs/s & BD actions/s: batched vs per-set, 2D N=2^17",
+        "value": R / (ms_step / 1000.0),
+        "unit": "interval pairs/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "2D flat causal diamond, N=131072, seed 3 (sprinkle+sort+link+count+action)",
+                   "N": N, "d": 2, "related_pairs": R, "abundances": [int(x) for x in n],
+                   "action": S, "count_path": {1: "pop", 2: "mfma"}[path_used]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "ensemble": ens,
+    }
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

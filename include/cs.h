@@ -1,0 +1,224 @@
+/*
+ * cs.h -- C ABI of the MI355X (gfx950) causal-set interval-abundance library.
+ *
+ * The library generates causal sets by sprinkling into flat causal diamonds,
+ * links them into a packed adjacency matrix, counts the elements inside the
+ * interval of every related pair, and evaluates the Benincasa-Dowker (BD)
+ * action, after W. J. Cunningham and D. Krioukov, "Causal Set Generator and
+ * Action Computer", arXiv:1709.03013.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Dimension d is the SPACETIME dimension: 2 = (1+1), 4 = (3+1).
+ *  - Elements carry labels 0..N-1 in a topological (time) order: a related
+ *    pair i<j always has i earlier (Sec. 2.2).
+ *  - Coordinates are structure-of-arrays float64: d arrays of N doubles.
+ *    2D: light-cone (u, v) in [0,1)^2, i<j related iff u_i<u_j and v_i<v_j.
+ *    4D: (t, x, y, z) in the diamond |x| < min(t, 1-t), related iff
+ *    dt*dt > (dx*dx + dy*dy) + dz*dz, evaluated in binary64 without fused
+ *    multiply-add (Sec. 1.1: timelike separation, strict).
+ *  - The causal matrix is symmetric with a zero diagonal (Sec. 2.2): row i
+ *    has W = cs_row_words(N) uint64 words (ceil(N/64) rounded up to a
+ *    multiple of 4, i.e. 256-bit rows, Sec. 3.2); column k is bit k%64 of
+ *    word k/64 (LSB first); padding bits are zero.
+ *  - Interval abundances: N_k = number of related pairs i<j with exactly k
+ *    elements l, i<l<j, related to both (Sec. 4.1; Fig. 2 and Alg. 5 compute
+ *    the same count as popcount(row i AND row j) over columns i+1..j-1).
+ *    The paper's n_i (inclusive order interval i) is N_{i-1}.
+ *  - Every call returns cs_status; nothing throws across the ABI.  On error
+ *    cs_last_error() returns a thread-local message (valid until the next
+ *    call on the same thread).  Results are bit-identical across paths, runs
+ *    and batch compositions: all counting is in integers.
+ *  - Thread safety: a context may be used from one thread at a time, except
+ *    the queue calls (cs_queue_*), which may be called concurrently.
+ */
+#ifndef CS_H
+#define CS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CS_OK = 0,
+  CS_EINVAL = 1,        /* bad argument: d not 2/4, N<0, bad stride, kmax<3 ... */
+  CS_ENOMEM = 2,        /* allocation would exceed the HBM budget, or failed */
+  CS_EDEVICE = 3,       /* a HIP runtime error */
+  CS_EBUSY = 4,         /* queue: result not ready yet */
+  CS_EUNSUPPORTED = 5   /* not available on this device / build */
+} cs_status;
+
+enum {
+  CS_PATH_AUTO = 0,     /* library picks POP or MFMA from density and size */
+  CS_PATH_POP = 1,      /* VALU AND + popcount kernel */
+  CS_PATH_MFMA = 2      /* int8 MFMA contraction (future x past) kernel */
+};
+
+typedef struct cs_ctx cs_ctx;
+typedef struct cs_set cs_set;
+
+/* Words per packed row for N elements: ceil(N/64) rounded up to 4. */
+int64_t cs_row_words(int64_t N);
+
+/* ---------------------------------------------------------------- context */
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
+ * memory the context may hold (0 = 90% of free memory at creation).
+ * hip_stream: a hipStream_t to run on, or NULL for a library-owned stream.
+ * The library owns the context; free with cs_destroy. */
+cs_status cs_create(cs_ctx** out, int device, uint64_t hbm_budget_bytes,
+                    void* hip_stream);
+void cs_destroy(cs_ctx* ctx);
+/* Thread-local message for the last failed call on this thread. */
+const char* cs_last_error(void);
+/* Bytes of device memory the context currently holds for live sets. */
+uint64_t cs_bytes_in_use(const cs_ctx* ctx);
+
+/* --------------------------------------------------------------- sprinkle */
+/* Sprinkle N elements into the flat diamond of dimension d from `seed` and
+ * sort them by time (Sec. 2.1, 2.2).  Random numbers: Philox4x64-10 at
+ * counter (c,0,0,0), key (seed, 1) in 2D / (seed, 2) in 4D; a word r gives
+ * the double (r>>11) 2^-53.  2D element c: u = dbl(r0), v = dbl(r1); sorted
+ * by t = (u+v)/2 (exact), then u, then c.  4D candidate c: t = dbl(r0),
+ * x,y,z = dbl(r1..r3) - 1/2, accepted iff (x*x+y*y)+z*z < m*m,
+ * m = min(t, 1-t); the first N accepted, sorted by t then acceptance rank.
+ * Creates a device-resident set (coordinates only; call cs_link next),
+ * owned by the library until cs_set_free.  N = 0 and N = 1 are valid. */
+cs_status cs_sprinkle(cs_ctx* ctx, int d, int64_t N, uint64_t seed,
+                      cs_set** out);
+
+/* Import coordinates (host, SoA, d*N doubles) already in a topological
+ * order: the caller's order becomes the labels.  The buffer is copied. */
+cs_status cs_set_from_coords(cs_ctx* ctx, int d, int64_t N,
+                             const double* coords, cs_set** out);
+
+/* Import a packed symmetric matrix (N rows of stride_words >= cs_row_words(N)
+ * words; on_device != 0 means `rows` is a device pointer).  The rows are
+ * copied into a W-word layout.  Labels must be a topological order of the
+ * order the matrix encodes (Sec. 4.3: the method works on any such matrix).
+ * validate != 0 checks symmetry, zero diagonal and zero padding on the
+ * device and returns CS_EINVAL if any fails.  d (2, 4, or 0 for "none") only
+ * selects the action weights. */
+cs_status cs_set_from_bitset(cs_ctx* ctx, int d, int64_t N,
+                             const uint64_t* rows, int64_t stride_words,
+                             int on_device, int validate, cs_set** out);
+
+void cs_set_free(cs_set* set);
+cs_status cs_set_info(const cs_set* set, int* d, int64_t* N, int64_t* W,
+                      int* linked);
+
+/* Copy the sorted coordinates (d*N doubles, SoA) and, if orig != NULL, the
+ * generation index of each sorted element, to host memory. */
+cs_status cs_get_coords(cs_ctx* ctx, const cs_set* set, double* coords,
+                        int64_t* orig);
+/* Copy the packed matrix (N*W words) to host memory. */
+cs_status cs_get_bitset(cs_ctx* ctx, const cs_set* set, uint64_t* rows);
+/* Device pointer of the packed matrix (N*W words), NULL if not linked.
+ * Valid until cs_set_free. */
+const uint64_t* cs_set_bitset_dev(const cs_set* set);
+
+/* ------------------------------------------------------------------- link */
+/* Build the packed causal matrix from the set's coordinates (Sec. 2.2):
+ * every pair tested, bits written in 64-bit words.  Allocates N*W*8 bytes
+ * inside the set; CS_ENOMEM if that exceeds the budget. */
+cs_status cs_link(cs_ctx* ctx, cs_set* set);
+
+/* ------------------------------------------------------------- abundances */
+/* Interval abundances of a linked set.  out[0..kmax] receives N_0..N_kmax
+ * (host memory, caller-owned, kmax+1 entries, kmax >= 3); R_out the number
+ * of related pairs, summ_out the sum of interior counts over related pairs
+ * (either may be NULL).  path: CS_PATH_AUTO / POP / MFMA; the result does not
+ * depend on it.  kmax is at most CS_KMAX_MAX. */
+#define CS_KMAX_MAX 4095
+cs_status cs_interval_abundances(cs_ctx* ctx, cs_set* set, int kmax,
+                                 uint64_t* out, uint64_t* R_out,
+                                 uint64_t* summ_out, int path);
+
+/* As above, plus the per-row-block breakdown: rows are grouped in blocks of
+ * CS_ROW_BLOCK labels; blocks[b*(kmax+3) + k] holds, for pairs i<j with i in
+ * block b, N_k (k = 0..kmax), then R, then the sum of interior counts.
+ * blocks is host memory of ceil(N/CS_ROW_BLOCK)*(kmax+3) words. */
+#define CS_ROW_BLOCK 256
+cs_status cs_interval_abundances_rows(cs_ctx* ctx, cs_set* set, int kmax,
+                                      uint64_t* blocks, int path);
+
+/* ----------------------------------------------------------------- action */
+/* Benincasa-Dowker action of a counted (or countable) set, using the set's d:
+ *   2D (Eq. 4):  S = 2 (N - 2 N_0 + 4 N_1 - 2 N_2)
+ *   4D (weights of the BD reference the paper cites for Eq. 4):
+ *                S = (4/sqrt 6) (N - N_0 + 9 N_1 - 16 N_2 + 8 N_3)
+ * in units of the discreteness scale.  The bracket is an exact 64-bit
+ * integer; the one multiplication by the prefactor is the only rounding.
+ * Counts the set (path AUTO) if it has not been counted yet.  CS_EINVAL if
+ * the set has d = 0. */
+cs_status cs_bd_action(cs_ctx* ctx, cs_set* set, double* S_out);
+
+/* ----------------------------------------------------- device-pointer tier */
+/* The caller owns all memory and the stream; calls are asynchronous on
+ * `hip_stream` (a hipStream_t; NULL = the legacy default stream).
+ * coords_dev: d*N doubles (SoA, topologically sorted).  bits_dev: N rows of
+ * stride_words (>= cs_row_words(N), multiple of 4) words. */
+cs_status cs_link_dev(int d, int64_t N, const double* coords_dev,
+                      uint64_t* bits_dev, int64_t stride_words,
+                      void* hip_stream);
+/* Count from a device matrix.  stats_dev receives kmax+3 uint64 words:
+ * N_0..N_kmax, R, sum of interior counts (device memory, overwritten).
+ * work_dev: device scratch of cs_count_workspace_bytes(N, kmax) bytes. */
+uint64_t cs_count_workspace_bytes(int64_t N, int kmax);
+cs_status cs_count_dev(const uint64_t* bits_dev, int64_t N,
+                       int64_t stride_words, int kmax, uint64_t* stats_dev,
+                       void* work_dev, int path, void* hip_stream);
+
+/* ---------------------------------------------------------------- batched */
+typedef struct {
+  int32_t d;        /* 2 or 4 */
+  int32_t reserved;
+  int64_t N;        /* elements, 0 <= N <= CS_BATCH_NMAX */
+  uint64_t seed;
+} cs_req;
+
+typedef struct {
+  uint64_t n[4];    /* N_0..N_3 */
+  uint64_t R;       /* related pairs */
+  uint64_t summ;    /* sum of interior counts */
+  double S;         /* BD action */
+  int32_t status;   /* cs_status of this set */
+  int32_t reserved;
+} cs_result;
+
+#define CS_BATCH_NMAX 16384
+/* Run a whole ensemble: every set is sprinkled, sorted, linked, counted and
+ * its action evaluated, with all sets sharing each launch (one persistent
+ * counting launch pulling (set, tile) work items from a device queue).  The
+ * launch sequence is captured once per batch shape in a hipGraph and
+ * replayed.  out[s] is the result of reqs[s]; identical to running the set
+ * alone.  Device memory comes from the context's pool (CS_ENOMEM if the
+ * batch does not fit the budget). */
+cs_status cs_batch_run(cs_ctx* ctx, int nsets, const cs_req* reqs,
+                       cs_result* out);
+
+/* ---------------------------------------------------------- queued serving */
+/* Continuous-batching request server on the context.  Requests are admitted
+ * in arrival order while their footprint (matrix + coordinates + scratch)
+ * fits under the budget and a slot is free; admitted requests run
+ * concurrently on the slots' streams.  Matrices stay resident (LRU) under the
+ * budget, keyed by (d, N, seed): a repeated request reuses its matrix.
+ * cs_queue_start sets the number of slots (concurrent requests on the GPU)
+ * and the budget for resident matrices (0 = the context budget). */
+cs_status cs_queue_start(cs_ctx* ctx, int slots, uint64_t resident_budget);
+cs_status cs_queue_submit(cs_ctx* ctx, const cs_req* req, uint64_t* ticket);
+/* CS_OK with *out filled when done, CS_EBUSY if not yet, CS_EINVAL for an
+ * unknown ticket.  timing (nullable, 3 doubles): submit->admit, admit->done,
+ * submit->done in seconds. */
+cs_status cs_queue_poll(cs_ctx* ctx, uint64_t ticket, cs_result* out,
+                        double* timing);
+/* Block until every submitted request is done. */
+cs_status cs_queue_drain(cs_ctx* ctx);
+/* Stop the server thread (also done by cs_destroy). */
+cs_status cs_queue_stop(cs_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CS_H */

@@ -1,0 +1,75 @@
+// cs_internal.h -- declarations shared by the library's translation units.
+//
+// Layout conventions (see include/cs.h): coordinates are SoA float64, the
+// matrix is N rows of W uint64 words, symmetric, zero diagonal, zero padding.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "cs.h"
+
+namespace cs {
+
+// One record of the time sort: primary key, secondary key, generation index.
+// 2D: k1 = a + b, k2 = a (u = a 2^-53, v = b 2^-53, t = (a+b) 2^-54 exactly).
+// 4D: k1 = r0 >> 11 (t = k1 2^-53), k2 = 0.  idx makes every key unique.
+struct SortRec {
+  uint64_t k1;
+  uint64_t k2;
+  uint64_t idx;
+};
+
+constexpr int kSortTile = 2048;  // records sorted per workgroup in LDS
+constexpr int kRowBlock = CS_ROW_BLOCK;
+
+inline int64_t row_words(int64_t N) {
+  int64_t w = (N + 63) / 64;
+  return (w + 3) / 4 * 4;
+}
+
+// Number of Philox candidates drawn for N accepted 4D points: the mean N/p
+// (p = pi/24, the acceptance probability) plus 8 standard deviations plus 256.
+int64_t candidates_4d(int64_t N);
+
+// ---- launchers (all asynchronous on `st`) --------------------------------
+// Sprinkle + sort: writes sorted SoA coords (d*N) and generation indices.
+// `scratch` must hold sprinkle_scratch_bytes(d, N, ncand) bytes.  For 4D the
+// number of accepted candidates is written to *accepted_dev (device); the
+// caller checks it against N (fewer means draw more candidates).
+size_t sprinkle_scratch_bytes(int d, int64_t N, int64_t ncand);
+hipError_t launch_sprinkle(int d, int64_t N, uint64_t seed, int64_t ncand,
+                           double* coords, int64_t* orig, void* scratch,
+                           uint64_t* accepted_dev, hipStream_t st);
+
+// Link: bits must hold N*W words; every word of every row is written.
+hipError_t launch_link(int d, int64_t N, const double* coords, uint64_t* bits,
+                       int64_t W, hipStream_t st);
+
+// Fill n uint64 words with v (a kernel, so it can sit in a captured graph).
+hipError_t launch_fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t st);
+
+// Counting.  rb_stats: nrb*(kmax+3) words, zero on entry; receives per
+// row-block histograms, R and sum of interior counts.
+int64_t num_row_blocks(int64_t N);
+hipError_t launch_count_pop(const uint64_t* bits, int64_t N, int64_t W,
+                            int kmax, uint64_t* rb_stats, hipStream_t st);
+hipError_t launch_count_mfma(const uint64_t* bits, int64_t N, int64_t W,
+                             int kmax, uint64_t* rb_stats, hipStream_t st);
+// Sum the row-block stats into tot (kmax+3 words).
+hipError_t launch_reduce_rows(const uint64_t* rb_stats, int64_t nrb,
+                              int kmax, uint64_t* tot, hipStream_t st);
+// Validate an imported matrix: writes 0 to *bad_dev if symmetric, zero
+// diagonal, zero padding; nonzero otherwise (bad_dev zeroed by the caller).
+hipError_t launch_validate(const uint64_t* bits, int64_t N, int64_t W,
+                           uint32_t* bad_dev, hipStream_t st);
+
+// Path choice for CS_PATH_AUTO.
+int choose_path(int64_t N, int kmax);
+
+// BD action from abundances (host): exact int64 bracket, one rounding.
+double bd_action(int d, int64_t N, const uint64_t* n);
+
+}  // namespace cs

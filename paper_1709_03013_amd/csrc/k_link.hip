@@ -1,0 +1,153 @@
+// k_link.hip -- the O(N^2) linking step (Sec. 2.2): the packed, symmetric,
+// zero-diagonal causal matrix from time-sorted coordinates.
+//
+// gfx950 design: a wave's 64 lanes are 64 consecutive columns k of one
+// 64-bit word; for each row i (wave-uniform, coordinates in scalar
+// registers) the 64 relation tests produce the word directly as the
+// wave's compare mask (ballot).  Word (i, w) is kept by lane i%64, so after
+// 64 rows every lane holds one word of a 64x64-word tile, which is staged in
+// LDS and stored row by row with fully coalesced 512-byte rows.
+//
+// Relation (Sec. 1.1, strict timelike separation), for either order of the
+// pair, so the symmetric matrix needs no index test:
+//   2D: (u_i < u_k and v_i < v_k) or (u_k < u_i and v_k < v_i);
+//   4D: dt*dt > (dx*dx + dy*dy) + dz*dz with d* = coordinate of k minus
+//       coordinate of i.  Rounding is sign-symmetric, so this equals the
+//       test written with the earlier element subtracted; dt*dt > 0 implies
+//       dt != 0, so equal times are unrelated.  No fused multiply-add.
+#include "cs_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace cs {
+namespace {
+
+template <int D>
+struct Pt {
+  double c[D];
+};
+
+template <int D>
+__device__ __forceinline__ bool related_sym(const Pt<D>& a, const Pt<D>& b) {
+  if constexpr (D == 2) {
+    return (a.c[0] < b.c[0] && a.c[1] < b.c[1]) ||
+           (b.c[0] < a.c[0] && b.c[1] < a.c[1]);
+  } else {
+    const double dt = b.c[0] - a.c[0];
+    const double dx = b.c[1] - a.c[1];
+    const double dy = b.c[2] - a.c[2];
+    const double dz = b.c[3] - a.c[3];
+    const double tt = dt * dt;
+    const double xx = dx * dx, yy = dy * dy, zz = dz * dz;
+    return tt > (xx + yy) + zz;
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_link(const double* __restrict__ coords,
+                                              int64_t N,
+                                              uint64_t* __restrict__ bits,
+                                              int64_t W) {
+  __shared__ uint64_t tile[64][65];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t i0 = (int64_t)blockIdx.y * 64;
+  const int64_t w0 = (int64_t)blockIdx.x * 64;
+  const int64_t rem = N - i0;
+  const int nrows = rem < 64 ? (int)rem : 64;
+  for (int wl = 0; wl < 16; ++wl) {
+    const int wloc = wave * 16 + wl;
+    const int64_t w = w0 + wloc;
+    uint64_t my = 0;
+    if (w < W) {
+      const int64_t k = w * 64 + lane;
+      const bool kval = k < N;
+      const int64_t kk = kval ? k : 0;
+      Pt<D> pk;
+#pragma unroll
+      for (int q = 0; q < D; ++q) pk.c[q] = coords[(int64_t)q * N + kk];
+      for (int r = 0; r < nrows; ++r) {
+        const int64_t i = i0 + r;
+        Pt<D> pi;
+#pragma unroll
+        for (int q = 0; q < D; ++q) pi.c[q] = coords[(int64_t)q * N + i];
+        const bool rel = kval && related_sym<D>(pi, pk);
+        const uint64_t m = __ballot(rel);
+        my = lane == r ? m : my;
+      }
+    }
+    tile[lane][wloc] = my;
+  }
+  __syncthreads();
+  for (int p = 0; p < 16; ++p) {
+    const int r = p * 4 + wave;
+    const int64_t i = i0 + r;
+    const int64_t w = w0 + lane;
+    if (i < N && w < W) bits[i * W + w] = tile[r][lane];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fill_u64(uint64_t* __restrict__ p,
+                                                  uint64_t v, size_t n) {
+  size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * 256;
+  for (; e < n; e += stride) p[e] = v;
+}
+
+// One thread per word (i, w): padding bits zero, diagonal bit zero, and every
+// set bit k has its mirror bit (k, i) set.
+__global__ __launch_bounds__(256) void k_validate(const uint64_t* __restrict__ bits,
+                                                  int64_t N, int64_t W,
+                                                  uint32_t* __restrict__ bad) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= N * W) return;
+  const int64_t i = e / W, w = e % W;
+  uint64_t x = bits[e];
+  uint32_t fault = 0;
+  const int64_t base = w * 64;
+  if (base + 64 > N) {
+    const uint64_t keep = base >= N ? 0ull : ((1ull << (N - base)) - 1);
+    if (x & ~keep) fault = 1;
+    x &= keep;
+  }
+  if ((i >> 6) == w && ((x >> (i & 63)) & 1ull)) fault = 1;
+  while (x) {
+    const int b = __ffsll((unsigned long long)x) - 1;
+    x &= x - 1;
+    const int64_t k = base + b;
+    if (!((bits[k * W + (i >> 6)] >> (i & 63)) & 1ull)) fault = 1;
+  }
+  if (fault) atomicOr(bad, 1u);
+}
+
+}  // namespace
+
+hipError_t launch_link(int d, int64_t N, const double* coords, uint64_t* bits,
+                       int64_t W, hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  dim3 grid((unsigned)((W + 63) / 64), (unsigned)((N + 63) / 64));
+  if (d == 2)
+    hipLaunchKernelGGL(k_link<2>, grid, dim3(256), 0, st, coords, N, bits, W);
+  else
+    hipLaunchKernelGGL(k_link<4>, grid, dim3(256), 0, st, coords, N, bits, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, st, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const uint64_t* bits, int64_t N, int64_t W,
+                           uint32_t* bad_dev, hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  const int64_t n = N * W;
+  hipLaunchKernelGGL(k_validate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     st, bits, N, W, bad_dev);
+  return hipGetLastError();
+}
+
+}  // namespace cs

@@ -1,0 +1,305 @@
+// k_sprinkle.hip -- sprinkling into flat causal diamonds and the time sort.
+//
+// Sec. 2.1 (coordinates drawn i.i.d. from the normalized volume form, in
+// parallel) and Sec. 2.2 (labels sorted by time so that the order is
+// topological).  Random numbers: Philox4x64-10 (Salmon et al., SC'11), one
+// block of four 64-bit words per element (2D) or candidate (4D), counter
+// (c,0,0,0), key (seed, 1) for 2D and (seed, 2) for 4D.
+//
+// 2D: u = (r0>>11) 2^-53, v = (r1>>11) 2^-53; with a = r0>>11, b = r1>>11 the
+//     time (u+v)/2 = (a+b) 2^-54 is exact, so the sort key is (a+b, a, c).
+// 4D: candidate c: t = dbl(r0), x,y,z = dbl(r1..r3) - 1/2, accepted iff
+//     (x*x + y*y) + z*z < m*m with m = min(t, 1-t) (binary64, no fused
+//     multiply-add).  The first N accepted in candidate order are the
+//     elements, sorted by (r0>>11, acceptance rank).
+//
+// Sort: each workgroup bitonic-sorts a tile of 2048 records in LDS; every
+// record then finds its global rank as its rank in its own tile plus the
+// number of smaller records in every other tile (binary search), and
+// scatters its coordinates there.  Keys are unique, so ranks are a
+// permutation.
+#include "cs_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace cs {
+namespace {
+
+constexpr uint64_t kM0 = 0xD2E7470EE14C6C93ull;
+constexpr uint64_t kM1 = 0xCA5A826395121157ull;
+constexpr uint64_t kW0 = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kW1 = 0xBB67AE8584CAA73Bull;
+
+__device__ __forceinline__ void philox10(uint64_t c[4], uint64_t k0,
+                                         uint64_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += kW0;
+      k1 += kW1;
+    }
+    const uint64_t lo0 = kM0 * c[0], hi0 = __umul64hi(kM0, c[0]);
+    const uint64_t lo1 = kM1 * c[2], hi1 = __umul64hi(kM1, c[2]);
+    const uint64_t n0 = hi1 ^ c[1] ^ k0;
+    const uint64_t n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+__device__ __forceinline__ double unit53(uint64_t r) {
+  return (double)(r >> 11) * 0x1.0p-53;
+}
+
+// 4D candidate test; returns the coordinates and the integer time key.
+__device__ __forceinline__ bool candidate4d(uint64_t c, uint64_t seed,
+                                            double xyz[4], uint64_t* kt) {
+  uint64_t r[4] = {c, 0, 0, 0};
+  philox10(r, seed, 2);
+  const double t = unit53(r[0]);
+  const double x = unit53(r[1]) - 0.5;
+  const double y = unit53(r[2]) - 0.5;
+  const double z = unit53(r[3]) - 0.5;
+  const double omt = 1.0 - t;
+  const double m = t < omt ? t : omt;
+  const double xx = x * x, yy = y * y, zz = z * z;
+  const double rho2 = (xx + yy) + zz;
+  const double mm = m * m;
+  xyz[0] = t;
+  xyz[1] = x;
+  xyz[2] = y;
+  xyz[3] = z;
+  *kt = r[0] >> 11;
+  return rho2 < mm;
+}
+
+__global__ __launch_bounds__(256) void k_keys2d(int64_t N, uint64_t seed,
+                                                SortRec* __restrict__ recs) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= N) return;
+  uint64_t r[4] = {(uint64_t)c, 0, 0, 0};
+  philox10(r, seed, 1);
+  const uint64_t a = r[0] >> 11, b = r[1] >> 11;
+  SortRec s;
+  s.k1 = a + b;
+  s.k2 = a;
+  s.idx = (uint64_t)c;
+  recs[c] = s;
+}
+
+__global__ __launch_bounds__(256) void k_count4d(int64_t ncand, uint64_t seed,
+                                                 uint32_t* __restrict__ blkcnt) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double xyz[4];
+  uint64_t kt;
+  const bool acc = c < ncand && candidate4d((uint64_t)c, seed, xyz, &kt);
+  const int n = __syncthreads_count(acc);
+  if (threadIdx.x == 0) blkcnt[blockIdx.x] = (uint32_t)n;
+}
+
+// Exclusive scan of nblk counts in one workgroup of 1024 threads; also the
+// total (number of accepted candidates).
+__global__ __launch_bounds__(1024) void k_scan_counts(
+    const uint32_t* __restrict__ blkcnt, int64_t nblk,
+    uint64_t* __restrict__ offs, uint64_t* __restrict__ total) {
+  __shared__ uint64_t part[1024];
+  const int tid = threadIdx.x;
+  const int64_t per = (nblk + 1023) / 1024;
+  const int64_t lo = tid * per;
+  const int64_t hi = lo + per < nblk ? lo + per : nblk;
+  uint64_t s = 0;
+  for (int64_t b = lo; b < hi; ++b) s += blkcnt[b];
+  part[tid] = s;
+  __syncthreads();
+  // Hillis-Steele inclusive scan over 1024 partial sums.
+  for (int d = 1; d < 1024; d <<= 1) {
+    const uint64_t v = tid >= d ? part[tid - d] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  uint64_t run = part[tid] - s;  // exclusive prefix of this thread's chunk
+  for (int64_t b = lo; b < hi; ++b) {
+    offs[b] = run;
+    run += blkcnt[b];
+  }
+  if (tid == 1023) *total = part[1023];
+}
+
+__global__ __launch_bounds__(256) void k_compact4d(
+    int64_t ncand, uint64_t seed, const uint64_t* __restrict__ offs, int64_t N,
+    SortRec* __restrict__ recs, double* __restrict__ raw) {
+  __shared__ uint32_t wcnt[4];
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double xyz[4];
+  uint64_t kt = 0;
+  const bool acc = c < ncand && candidate4d((uint64_t)c, seed, xyz, &kt);
+  const uint64_t bal = __ballot(acc);
+  const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+      (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+  if (lane == 0) wcnt[wave] = (uint32_t)__popcll(bal);
+  __syncthreads();
+  uint32_t woff = 0;
+  for (int q = 0; q < wave; ++q) woff += wcnt[q];
+  const int64_t e = (int64_t)(offs[blockIdx.x] + woff + below);
+  if (acc && e < N) {
+    SortRec s;
+    s.k1 = kt;
+    s.k2 = 0;
+    s.idx = (uint64_t)e;
+    recs[e] = s;
+    raw[e] = xyz[0];
+    raw[N + e] = xyz[1];
+    raw[2 * N + e] = xyz[2];
+    raw[3 * N + e] = xyz[3];
+  }
+}
+
+__device__ __forceinline__ bool rec_less(const SortRec& a, const SortRec& b) {
+  if (a.k1 != b.k1) return a.k1 < b.k1;
+  if (a.k2 != b.k2) return a.k2 < b.k2;
+  return a.idx < b.idx;
+}
+
+__global__ __launch_bounds__(1024) void k_tile_sort(SortRec* __restrict__ recs,
+                                                    int64_t N) {
+  __shared__ SortRec s[kSortTile];
+  const int tid = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  const int64_t n = N - base < kSortTile ? N - base : kSortTile;
+  for (int q = tid; q < kSortTile; q += 1024) {
+    if (q < n) {
+      s[q] = recs[base + q];
+    } else {
+      s[q].k1 = ~0ull;
+      s[q].k2 = ~0ull;
+      s[q].idx = ~0ull;
+    }
+  }
+  __syncthreads();
+  for (int k = 2; k <= kSortTile; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int q = tid; q < kSortTile; q += 1024) {
+        const int p = q ^ j;
+        if (p > q) {
+          const bool up = (q & k) == 0;
+          SortRec x = s[q], y = s[p];
+          if (rec_less(y, x) == up) {
+            s[q] = y;
+            s[p] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int q = tid; q < n; q += 1024) recs[base + q] = s[q];
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_rank_scatter(
+    const SortRec* __restrict__ recs, int64_t N, const double* __restrict__ raw,
+    double* __restrict__ coords, int64_t* __restrict__ orig) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= N) return;
+  const SortRec my = recs[e];
+  if (my.idx >= (uint64_t)N) return;  // unfilled record (too few 4D draws)
+  const int64_t mytile = e / kSortTile;
+  int64_t rank = e - mytile * kSortTile;
+  const int64_t ntiles = (N + kSortTile - 1) / kSortTile;
+  for (int64_t u = 0; u < ntiles; ++u) {
+    if (u == mytile) continue;
+    const int64_t lo = u * kSortTile;
+    int64_t len = N - lo < kSortTile ? N - lo : kSortTile;
+    // number of records in tile u that are smaller than mine
+    int64_t a = 0, b = len;
+    while (a < b) {
+      const int64_t mid = (a + b) >> 1;
+      if (rec_less(recs[lo + mid], my)) a = mid + 1;
+      else b = mid;
+    }
+    rank += a;
+  }
+  orig[rank] = (int64_t)my.idx;
+  if (D == 2) {
+    coords[rank] = (double)my.k2 * 0x1.0p-53;
+    coords[N + rank] = (double)(my.k1 - my.k2) * 0x1.0p-53;
+  } else {
+    for (int q = 0; q < 4; ++q) coords[(int64_t)q * N + rank] = raw[(int64_t)q * N + my.idx];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fill_recs(SortRec* __restrict__ recs,
+                                                   int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < n) {
+    recs[e].k1 = ~0ull;
+    recs[e].k2 = ~0ull;
+    recs[e].idx = ~0ull;
+  }
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+int64_t candidates_4d(int64_t N) {
+  const double p = 3.14159265358979323846 / 24.0;
+  const double mean = (double)N / p;
+  const double sd = __builtin_sqrt(mean * (1.0 - p));
+  return (int64_t)(mean + 8.0 * sd) + 256;
+}
+
+size_t sprinkle_scratch_bytes(int d, int64_t N, int64_t ncand) {
+  size_t b = align256((size_t)N * sizeof(SortRec));
+  if (d == 4) {
+    const int64_t nblk = (ncand + 255) / 256;
+    b += align256((size_t)N * 4 * sizeof(double));
+    b += align256((size_t)nblk * sizeof(uint32_t));
+    b += align256((size_t)nblk * sizeof(uint64_t));
+  }
+  return b;
+}
+
+hipError_t launch_sprinkle(int d, int64_t N, uint64_t seed, int64_t ncand,
+                           double* coords, int64_t* orig, void* scratch,
+                           uint64_t* accepted_dev, hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  char* p = (char*)scratch;
+  SortRec* recs = (SortRec*)p;
+  p += align256((size_t)N * sizeof(SortRec));
+  const unsigned gN = (unsigned)((N + 255) / 256);
+  const double* raw = nullptr;
+  if (d == 2) {
+    hipLaunchKernelGGL(k_keys2d, dim3(gN), dim3(256), 0, st, N, seed, recs);
+  } else {
+    double* rawm = (double*)p;
+    p += align256((size_t)N * 4 * sizeof(double));
+    const int64_t nblk = (ncand + 255) / 256;
+    uint32_t* blkcnt = (uint32_t*)p;
+    p += align256((size_t)nblk * sizeof(uint32_t));
+    uint64_t* offs = (uint64_t*)p;
+    hipLaunchKernelGGL(k_fill_recs, dim3(gN), dim3(256), 0, st, recs, N);
+    hipLaunchKernelGGL(k_count4d, dim3((unsigned)nblk), dim3(256), 0, st, ncand,
+                       seed, blkcnt);
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, blkcnt, nblk,
+                       offs, accepted_dev);
+    hipLaunchKernelGGL(k_compact4d, dim3((unsigned)nblk), dim3(256), 0, st,
+                       ncand, seed, offs, N, recs, rawm);
+    raw = rawm;
+  }
+  const unsigned ntiles = (unsigned)((N + kSortTile - 1) / kSortTile);
+  hipLaunchKernelGGL(k_tile_sort, dim3(ntiles), dim3(1024), 0, st, recs, N);
+  if (d == 2)
+    hipLaunchKernelGGL(k_rank_scatter<2>, dim3(gN), dim3(256), 0, st, recs, N,
+                       raw, coords, orig);
+  else
+    hipLaunchKernelGGL(k_rank_scatter<4>, dim3(gN), dim3(256), 0, st, recs, N,
+                       raw, coords, orig);
+  return hipGetLastError();
+}
+
+}  // namespace cs

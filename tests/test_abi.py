@@ -1,0 +1,89 @@
+"""The C-ABI library loads and exports every symbol include/cs.h declares
+(CPU only: no compute calls), and its argument checks run before any device
+work."""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cs.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(cs_[a-z_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1709_03013_amd as p
+    return p
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ["cs_create", "cs_destroy", "cs_last_error", "cs_sprinkle", "cs_link",
+                 "cs_interval_abundances", "cs_bd_action", "cs_set_from_bitset", "cs_get_bitset",
+                 "cs_get_coords", "cs_link_dev", "cs_count_dev", "cs_batch_run",
+                 "cs_queue_submit", "cs_queue_poll", "cs_queue_drain"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    so = lib._binding.LIB_PATH
+    out = subprocess.run(["nm", "-D", "--defined-only", so], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (cs_[a-z_]+)\b", out))
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol(lib):
+    assert sorted(lib.exported_symbols()) == declared_functions()
+    L = lib.lib()
+    for n in declared_functions():
+        assert hasattr(L, n)
+
+
+def test_row_words(lib):
+    assert lib.cs_row_words(0) == 0
+    assert lib.cs_row_words(1) == 4
+    assert lib.cs_row_words(64) == 4
+    assert lib.cs_row_words(257) == 8
+    assert lib.cs_row_words(1024) == 16
+    assert lib.cs_row_words(131072) == 2048
+
+
+def test_argument_errors_need_no_device(lib):
+    with pytest.raises(lib.CsError) as e:
+        lib.cs_link_dev(3, 10, 0, 0, 4, None)
+    assert e.value.status == lib._binding.CS_EINVAL
+    with pytest.raises(lib.CsError) as e:
+        lib.cs_link_dev(2, 100, 1, 1, 3, None)          # stride too small
+    assert e.value.status == lib._binding.CS_EINVAL
+    with pytest.raises(lib.CsError) as e:
+        lib.cs_count_dev(1, 100, 4, 2, 1, 1, 0, None)   # kmax < 3
+    assert e.value.status == lib._binding.CS_EINVAL
+    with pytest.raises(lib.CsError) as e:
+        lib.cs_count_dev(1, 100, 4, 3, 1, 1, 7, None)   # bad path
+    assert e.value.status == lib._binding.CS_EINVAL
+    assert lib.cs_count_workspace_bytes(1000, 3) == 4 * 6 * 8
+
+
+def test_no_device_is_an_error_not_a_fallback(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(lib.CsError) as e:
+        lib.cs_create(0)
+    assert e.value.status in (lib._binding.CS_EDEVICE, lib._binding.CS_EINVAL)
+
+
+def test_struct_layouts(lib):
+    import ctypes
+    b = lib._binding
+    assert ctypes.sizeof(b.cs_req) == 24
+    assert ctypes.sizeof(b.cs_result) == 4 * 8 + 8 + 8 + 8 + 8
