@@ -1,10 +1,278 @@
-// k_count_mfma.hip -- interval counting as an int8 MFMA contraction.
+// k_count_mfma.hip -- interval counting as an int8 matrix-core contraction.
+//
+// With U the strictly upper-triangular part of the causal matrix (U[i][k] = 1
+// iff i < k and i ~ k), the number of elements inside the interval of a pair
+// i < j is m_ij = sum_k U[i][k] U[k][j]: exactly the masked AND + popcount of
+// Fig. 2 / Alg. 5, written as an integer matrix product.  Because the stored
+// matrix is symmetric, U[k][j] = bit k of row j for k < j, so both operands
+// are rows of the packed matrix: row i masked to columns > i ("future of i")
+// and row j masked to columns < j ("past of j"), contracted over k.  0/1
+// products summed in int32 are exact (m <= N - 2 < 2^31).
+//
+// gfx950 design: v_mfma_i32_32x32x32_i8.  A workgroup of 8 waves owns a
+// 256x256 tile of pairs (row block BI <= column block BJ) and walks the
+// 64-bit words 4BI .. 4BJ+3 of its 512 rows (only there can both masks be
+// nonzero).  Each of its 8 waves computes 128x64 pairs as 4x2 MFMA tiles.  Per word,
+// lane l reads word w of its row (l%32) for each of its 4 A and 4 B
+// fragments and keeps the half selected by l/32; the 32 bits D are spread to
+// bytes as (D >> r) & 0x01010101, r = 0..7: dwords 0-3 feed the first MFMA,
+// 4-7 the second.  A and B use the same spreading, and the hardware uses the
+// same k order for A and B, so every bit of the word meets its partner
+// exactly once: two MFMAs per word contract all 64 columns.  Masks are only
+// applied in the four words of each diagonal block.  The epilogue keeps pairs
+// with i < j and bit (i, j) set, bins m, and adds R and the sum of m, with
+// one atomic per counter per wave into the tile's row-block stats.
+#include <cstdlib>
+
+#include "cs_device.h"
 #include "cs_internal.h"
 
 namespace cs {
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr int kBT = 256;  // pairs per block-tile side (= row block)
+
+// Columns of word w strictly above label i.
+__device__ __forceinline__ uint64_t mask_above(int64_t i, int64_t w) {
+  const int64_t wi = i >> 6;
+  if (w < wi) return 0ull;
+  if (w > wi) return ~0ull;
+  return ~((2ull << (i & 63)) - 1);
+}
+
+// Columns of word w strictly below label j.
+__device__ __forceinline__ uint64_t mask_below(int64_t j, int64_t w) {
+  const int64_t wj = j >> 6;
+  if (w > wj) return 0ull;
+  if (w < wj) return ~0ull;
+  return (1ull << (j & 63)) - 1;
+}
+
+// Bits r0..r0+3 (each with +8, +16, +24) of D as one 16-byte MFMA operand of
+// 0/1 bytes: dword q holds bits r0+q, r0+q+8, r0+q+16, r0+q+24.
+__device__ __forceinline__ v4i spread4(uint32_t D, int r0) {
+  const uint32_t M = 0x01010101u;
+  v4i f;
+  f[0] = (int)((D >> r0) & M);
+  f[1] = (int)((D >> (r0 + 1)) & M);
+  f[2] = (int)((D >> (r0 + 2)) & M);
+  f[3] = (int)((D >> (r0 + 3)) & M);
+  return f;
+}
+
+// WM x WN waves over the 256x256 tile; each wave owns (256/WM) x (256/WN)
+// pairs as TM x TN tiles of 32x32.
+template <int WM, int WN, bool FULL>
+__global__ __launch_bounds__(64 * WM * WN, 1) void k_count_mfma(
+    const uint64_t* __restrict__ bits, int64_t N, int64_t W, int64_t nb,
+    int kmax, uint64_t* __restrict__ rb_stats) {
+  constexpr int kThreads = 64 * WM * WN;
+  constexpr int TM = kBT / WM / 32;
+  constexpr int TN = kBT / WN / 32;
+  extern __shared__ uint32_t lds_hist[];  // FULL only: kmax+2 bins
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int r32 = lane & 31, g = lane >> 5;
+  int64_t BI, BJ;
+  tri_tile_longest_first((int64_t)blockIdx.x, nb, &BI, &BJ);
+  if constexpr (FULL) {
+    for (int b = tid; b <= kmax + 1; b += kThreads) lds_hist[b] = 0;
+    __syncthreads();
+  }
+  const int64_t I0 = BI * kBT + (wave / WN) * (32 * TM);
+  const int64_t J0 = BJ * kBT + (wave % WN) * (32 * TN);
+
+  // Words are consumed in chunks of four (32 bytes of every row).  Lane
+  // group g reads the 16 bytes holding words 2g and 2g+1 of the chunk for its
+  // row l%32 of every A and B tile.  Addresses are a uniform base (the block
+  // tile's first row, which always exists) plus a 32-bit per-lane offset;
+  // rows past N read that first row instead: their pairs are dropped in the
+  // epilogue, so the values never matter.
+  const char* abase = (const char*)(bits + BI * kBT * W) + 16 * g;
+  const char* bbase = (const char*)(bits + BJ * kBT * W) + 16 * g;
+  uint32_t aoffs[TM], boffs[TN];
+#pragma unroll
+  for (int t = 0; t < TM; ++t) {
+    const int64_t rel = I0 - BI * kBT + 32 * t + r32;
+    aoffs[t] = BI * kBT + rel < N ? (uint32_t)(rel * W * 8) : 0u;
+  }
+#pragma unroll
+  for (int t = 0; t < TN; ++t) {
+    const int64_t rel = J0 - BJ * kBT + 32 * t + r32;
+    boffs[t] = BJ * kBT + rel < N ? (uint32_t)(rel * W * 8) : 0u;
+  }
+
+  v16i acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[a][b][v] = 0;
+
+  const int64_t c0 = BI, c1 = BJ;  // chunk index = block index (4 words each)
+  uint4 na[TM], nbw[TN];
+  auto load_chunk = [&](int64_t c) {
+    const char* pa = abase + c * 32;
+    const char* pb = bbase + c * 32;
+#pragma unroll
+    for (int t = 0; t < TM; ++t) na[t] = *(const uint4*)(pa + aoffs[t]);
+#pragma unroll
+    for (int t = 0; t < TN; ++t) nbw[t] = *(const uint4*)(pb + boffs[t]);
+  };
+  // One chunk: issue the next chunk's loads, mask (diagonal chunks only),
+  // spread to int8 and run eight MFMAs per tile pair.  Dword q of a lane's
+  // 16 bytes is half q&1 of word 4c + 2g + q/2.
+  auto step = [&](int64_t c, bool mask_a, bool mask_b) {
+    uint32_t xa[TM][4], xb[TN][4];
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+      xa[t][0] = na[t].x; xa[t][1] = na[t].y; xa[t][2] = na[t].z; xa[t][3] = na[t].w;
+    }
+#pragma unroll
+    for (int t = 0; t < TN; ++t) {
+      xb[t][0] = nbw[t].x; xb[t][1] = nbw[t].y; xb[t][2] = nbw[t].z; xb[t][3] = nbw[t].w;
+    }
+    load_chunk(c < c1 ? c + 1 : c1);
+    if (mask_a) {
+#pragma unroll
+      for (int t = 0; t < TM; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          xa[t][q] &= (uint32_t)(mask_above(I0 + 32 * t + r32, 4 * c + 2 * g + (q >> 1)) >> (32 * (q & 1)));
+    }
+    if (mask_b) {
+#pragma unroll
+      for (int t = 0; t < TN; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          xb[t][q] &= (uint32_t)(mask_below(J0 + 32 * t + r32, 4 * c + 2 * g + (q >> 1)) >> (32 * (q & 1)));
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        v4i fa[TM], fb[TN];
+#pragma unroll
+        for (int t = 0; t < TM; ++t) fa[t] = spread4(xa[t][q], 4 * h);
+#pragma unroll
+        for (int t = 0; t < TN; ++t) fb[t] = spread4(xb[t][q], 4 * h);
+#pragma unroll
+        for (int a = 0; a < TM; ++a)
+#pragma unroll
+          for (int b = 0; b < TN; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
+      }
+  };
+  load_chunk(c0);
+  if (c0 == c1) {
+    step(c0, true, true);
+  } else {
+    step(c0, true, false);
+    for (int64_t c = c0 + 1; c < c1; ++c) step(c, false, false);
+    step(c1, false, true);
+  }
+
+  // Epilogue.  Lane l holds column j = J0 + 32b + l%32 and rows
+  // i = I0 + 32a + 8(v/4) + 4(l/32) + v%4 of tile (a, b); the relation bit
+  // (i, j) is bit i of row j (all 32 rows of a tile share one word of row j).
+  // In a diagonal tile the bits of rows i >= j are cleared first, so every
+  // test below is a plain bit test.  With FULL, pairs that are not counted
+  // add to a spare bin kmax+1 so the LDS atomics need no branch.
+  uint32_t cnt[4] = {0, 0, 0, 0};
+  uint32_t nrel = 0;
+  uint64_t summ = 0;
+#pragma unroll
+  for (int b = 0; b < TN; ++b) {
+    const int64_t j = J0 + 32 * b + r32;
+#pragma unroll
+    for (int a = 0; a < TM; ++a) {
+      const int64_t ibase = I0 + 32 * a;
+      const uint64_t rw = j < N ? bits[j * W + (ibase >> 6)] : 0ull;
+      uint32_t r = (uint32_t)(rw >> (ibase & 63));
+      if (BI == BJ) {
+        const int64_t lim = j - ibase;  // rows ri < lim have i < j
+        r &= lim >= 32 ? ~0u : (lim <= 0 ? 0u : ((1u << lim) - 1u));
+      }
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int ri = 8 * (v >> 2) + 4 * g + (v & 3);
+        const bool valid = (r >> ri) & 1u;
+        const uint32_t m = (uint32_t)acc[a][b][v];
+        nrel += valid ? 1u : 0u;
+        summ += valid ? m : 0u;
+        if constexpr (FULL) {
+          const bool hit = valid && m <= (uint32_t)kmax;
+          atomicAdd(&lds_hist[hit ? m : (uint32_t)kmax + 1], 1u);
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) cnt[k] += (valid && m == (uint32_t)k) ? 1u : 0u;
+        }
+      }
+    }
+  }
+  nrel = wave_sum_u32(nrel);
+  summ = wave_sum_u64(summ);
+  uint64_t* st = rb_stats + BI * (int64_t)(kmax + 3);
+  if constexpr (!FULL) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cnt[k] = wave_sum_u32(cnt[k]);
+    if (lane < 4) {
+      const uint32_t v = lane == 0 ? cnt[0] : lane == 1 ? cnt[1] : lane == 2 ? cnt[2] : cnt[3];
+      if (v) atomicAdd((unsigned long long*)&st[lane], (unsigned long long)v);
+    }
+  } else {
+    __syncthreads();
+    for (int b = tid; b <= kmax; b += kThreads) {
+      const uint32_t v = lds_hist[b];
+      if (v) atomicAdd((unsigned long long*)&st[b], (unsigned long long)v);
+    }
+  }
+  if (lane == 0) {
+    if (nrel) atomicAdd((unsigned long long*)&st[kmax + 1], (unsigned long long)nrel);
+    if (summ) atomicAdd((unsigned long long*)&st[kmax + 2], (unsigned long long)summ);
+  }
+}
+
+template <int WM, int WN>
+hipError_t launch_variant(const uint64_t* bits, int64_t N, int64_t W, int kmax,
+                          uint64_t* rb_stats, hipStream_t st) {
+  const int64_t nb = (N + kBT - 1) / kBT;
+  const int64_t ntiles = nb * (nb + 1) / 2;
+  if (ntiles > 0x7fffffffLL) return hipErrorInvalidValue;
+  const dim3 block(64 * WM * WN);
+  if (kmax <= 3) {
+    hipLaunchKernelGGL((k_count_mfma<WM, WN, false>), dim3((unsigned)ntiles), block, 0, st,
+                       bits, N, W, nb, kmax, rb_stats);
+  } else {
+    const size_t lds = (size_t)(kmax + 2) * sizeof(uint32_t);
+    hipLaunchKernelGGL((k_count_mfma<WM, WN, true>), dim3((unsigned)ntiles), block, lds, st,
+                       bits, N, W, nb, kmax, rb_stats);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// 0: 2x2 waves of 128x128 pairs, 1 (default, faster on MI355X): 2x4 waves of
+// 128x64 pairs
+static int mfma_variant() {
+  static int v = [] {
+    const char* e = getenv("CS_MFMA_VARIANT");
+    return e ? atoi(e) : 1;
+  }();
+  return v;
+}
+
 hipError_t launch_count_mfma(const uint64_t* bits, int64_t N, int64_t W, int kmax,
                              uint64_t* rb_stats, hipStream_t st) {
-  (void)bits; (void)N; (void)W; (void)kmax; (void)rb_stats; (void)st;
-  return hipErrorNotSupported;
+  static_assert(kBT == kRowBlock, "block tile must equal the stats row block");
+  if (N <= 1) return hipSuccess;
+  if (mfma_variant() == 1) return launch_variant<2, 4>(bits, N, W, kmax, rb_stats, st);
+  return launch_variant<2, 2>(bits, N, W, kmax, rb_stats, st);
 }
+
 }  // namespace cs

@@ -19,44 +19,13 @@
 // the tile's row-block stats with one atomic each.
 //
 // Tiles run longest-first (decreasing bj - bi) to shorten the tail.
+#include "cs_device.h"
 #include "cs_internal.h"
 
 namespace cs {
 namespace {
 
 constexpr int kChunk = 4;  // words per staging step (rows are 4-word aligned)
-
-__device__ __forceinline__ void tile_of(int64_t t, int64_t nb, int64_t* bi,
-                                        int64_t* bj) {
-  // Group q (1..nb) holds the q tiles with bj - bi = nb - q; it starts at
-  // index q(q-1)/2.
-  int64_t q = (int64_t)((__builtin_sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5) + 1;
-  while (q > 1 && (q - 1) * q / 2 > t) --q;
-  while (q * (q + 1) / 2 <= t) ++q;
-  const int64_t off = t - (q - 1) * q / 2;
-  *bi = off;
-  *bj = off + (nb - q);
-}
-
-// popcount(x) + c as one v_bcnt_u32_b32 (keeps the accumulation chained
-// instead of letting the compiler regroup it into extra v_add3 ops).
-__device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t c) {
-  uint32_t r;
-  asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(c));
-  return r;
-}
-
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 template <bool FULL>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_count_pop(
@@ -69,7 +38,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
   const int lane = threadIdx.x;
   const int li = lane >> 3, lj = lane & 7;
   int64_t bi, bj;
-  tile_of((int64_t)blockIdx.x, nb, &bi, &bj);
+  tri_tile_longest_first((int64_t)blockIdx.x, nb, &bi, &bj);
 
   if constexpr (FULL) {
     for (int b = lane; b <= kmax; b += 64) lds_hist[b] = 0;

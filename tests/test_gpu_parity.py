@@ -71,7 +71,7 @@ def test_sprinkle_and_link_match_oracle(cs, ctx, d, N, seed):
 
 
 # ------------------------------------------------------------------- counts
-@pytest.mark.parametrize("path", [1])
+@pytest.mark.parametrize("path", [1, 2])
 @pytest.mark.parametrize("d,N,seed", [(2, 2, 1), (2, 3, 2), (2, 64, 3), (2, 65, 4), (2, 200, 5),
                                       (2, 1024, 1), (2, 1500, 12), (4, 64, 6), (4, 300, 7),
                                       (4, 2048, 14), (4, 2500, 15)])
@@ -90,7 +90,7 @@ def test_counts_match_oracle(cs, ctx, d, N, seed, path):
         cs.cs_set_free(s)
 
 
-@pytest.mark.parametrize("path", [1])
+@pytest.mark.parametrize("path", [1, 2])
 @pytest.mark.parametrize("kmax", [4, 17, 200])
 @pytest.mark.parametrize("d,N,seed", [(2, 700, 31), (4, 1100, 32)])
 def test_full_histogram_matches_oracle(cs, ctx, d, N, seed, kmax, path):
@@ -105,7 +105,7 @@ def test_full_histogram_matches_oracle(cs, ctx, d, N, seed, kmax, path):
         cs.cs_set_free(s)
 
 
-@pytest.mark.parametrize("path", [1])
+@pytest.mark.parametrize("path", [1, 2])
 def test_row_block_stats_match_oracle(cs, ctx, path):
     d, N, seed = 2, 1300, 41
     say("case rowblocks N=%d path=%d" % (N, path))
@@ -136,7 +136,7 @@ def injected_cases():
     ]
 
 
-@pytest.mark.parametrize("path", [1])
+@pytest.mark.parametrize("path", [1, 2])
 @pytest.mark.parametrize("name,order", injected_cases(), ids=[c[0] for c in injected_cases()])
 def test_injected_orders(cs, ctx, name, order, path):
     say("case injected %s path=%d" % (name, path))
@@ -251,7 +251,7 @@ def golden(name):
     return g[name]
 
 
-@pytest.mark.parametrize("path", [0, 1])
+@pytest.mark.parametrize("path", [0, 1, 2])
 @pytest.mark.parametrize("name", ["2d_1024", "4d_16384"])
 def test_workload_matches_stored_oracle(cs, ctx, name, path):
     g = golden(name)
