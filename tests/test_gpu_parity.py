@@ -266,3 +266,33 @@ def test_workload_matches_stored_oracle(cs, ctx, name, path):
         assert hashlib.sha256(cs.cs_get_bitset(ctx, s).tobytes()).hexdigest() == g["bitset_sha256"]
     finally:
         cs.cs_set_free(s)
+
+
+def test_full_size_2d_131072_against_stored_oracle(cs, ctx):
+    """The 2 GiB workload in the launch configuration bench.py times: matrix
+    bytes (sha256), abundances, R, sum of m and action equal the stored oracle
+    results (tests/golden/make_golden.py --large); the per-row-block
+    breakdown sums to the totals, and two sampled row blocks equal the
+    oracle's count over the same rows."""
+    import hashlib
+    g = golden("2d_131072")
+    N = g["N"]
+    say("case full-size 2D N=%d" % N)
+    s = gpu_set(cs, ctx, g["d"], N, g["seed"])
+    try:
+        bits = cs.cs_get_bitset(ctx, s)
+        assert hashlib.sha256(bits.tobytes()).hexdigest() == g["bitset_sha256"]
+        for path in (0, 2, 1):
+            say("  path %d" % path)
+            n, R, sm = cs.cs_interval_abundances(ctx, s, 3, path)
+            assert [int(x) for x in n] == g["n"] and R == g["R"] and sm == g["summ"]
+        assert cs.cs_bd_action(ctx, s) == float.fromhex(g["S"])
+        blocks = cs.cs_interval_abundances_rows(ctx, s, 3, 0)
+        tot = blocks.sum(axis=0)
+        assert [int(x) for x in tot[:4]] == g["n"] and int(tot[4]) == g["R"] and int(tot[5]) == g["summ"]
+        for b in (0, blocks.shape[0] // 2 + 7):
+            say("  oracle row block %d" % b)
+            h, R, sm = oracle.count_bits(bits, N, nbins=4, rows=(b * 256, b * 256 + 256))
+            assert list(blocks[b, :4]) == list(h) and blocks[b, 4] == R and blocks[b, 5] == sm
+    finally:
+        cs.cs_set_free(s)
