@@ -153,7 +153,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--path", type=int, default=1, help="0 auto, 1 popcount, 2 MFMA")
+    ap.add_argument("--path", type=int, default=0, help="0 auto, 1 popcount, 2 MFMA")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-span", action="store_true")

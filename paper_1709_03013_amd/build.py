@@ -25,6 +25,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-mcode-object-version=5", "-O3", "-fPIC", "-std=c++17",
     "-ffp-contract=off", "-fno-fast-math",
+    # keep atomics as written: the combiner wraps a wave's atomic in a
+    # first-lane branch, which must not appear inside persistent work loops
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,

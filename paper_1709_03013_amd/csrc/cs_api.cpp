@@ -45,9 +45,9 @@ double bd_action(int d, int64_t N, const uint64_t* n) {
 
 int choose_path(int64_t N, int kmax) {
   (void)kmax;
-  // The MFMA contraction wins once tiles are large enough to amortize the
-  // bit unpacking; below that the popcount kernel has less waste.
-  return CS_PATH_POP;
+  // Measured on MI355X: the popcount kernel wins up to N ~ 4096 (launch-bound
+  // sizes, less tile waste), the MFMA contraction from N ~ 8192 on.
+  return N >= 6144 ? CS_PATH_MFMA : CS_PATH_POP;
 }
 
 // ---------------------------------------------------------------- Pool
@@ -180,6 +180,7 @@ cs_status cs_create(cs_ctx** out, int device, uint64_t hbm_budget_bytes, void* h
     hbm_budget_bytes = (uint64_t)(0.9 * (double)fr);
   }
   c->pool.budget = hbm_budget_bytes;
+  c->tuner = std::unique_ptr<Tuner, void (*)(Tuner*)>(new_tuner(), destroy_tuner);
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
     c->own_stream = false;
@@ -427,6 +428,7 @@ cs_status cs_interval_abundances(cs_ctx* ctx, cs_set* s, int kmax, uint64_t* out
   if (!out) return fail(CS_EINVAL, "cs_interval_abundances: out is NULL");
   (void)hipSetDevice(ctx->device);
   std::vector<uint64_t> tot((size_t)kmax + 3, 0);
+  if (path == CS_PATH_AUTO && (s->d == 2 || s->d == 4)) path = tuned_path(ctx, s->d, s->N);
   if (s->N > 1) {
     rc = count_matrix(ctx, s->bits, s->N, s->W, kmax, path, tot.data(), nullptr, ctx->stream);
     if (rc != CS_OK) return rc;

@@ -40,4 +40,15 @@ __device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t c) {
   return r;
 }
 
+// Next work item of a persistent workgroup's queue, the same value in every
+// lane.  Every lane issues the atomic but only lane 0 adds 1, so lane 0 gets
+// the head before its own increment whatever order the lanes are applied in;
+// there is no lane-dependent branch, so the compiler cannot let lanes leave
+// a persistent loop in different iterations.  (Kernels using this are built
+// with the atomic combiner off, which would reintroduce such a branch.)
+__device__ __forceinline__ uint32_t next_item(uint32_t* head) {
+  const uint32_t v = atomicAdd(head, threadIdx.x == 0 ? 1u : 0u);
+  return __builtin_amdgcn_readlane(v, 0);
+}
+
 }  // namespace cs

@@ -69,6 +69,57 @@ hipError_t launch_validate(const uint64_t* bits, int64_t N, int64_t W,
 // Path choice for CS_PATH_AUTO.
 int choose_path(int64_t N, int kmax);
 
+// ---- batched ensembles -----------------------------------------------------
+// One set of a batch, as the device sees it.  Offsets index the arena arrays.
+struct BatchSet {
+  int32_t d;
+  int32_t path;        // CS_PATH_POP or CS_PATH_MFMA
+  int64_t N, W;
+  uint64_t seed;
+  int64_t coords_off;  // doubles into coords (d*N)
+  int64_t orig_off;    // int64 into orig (N)
+  int64_t rec_off;     // records into recs (N)
+  int64_t raw_off;     // doubles into raw (4*N, 4D only)
+  int64_t bits_off;    // words into bits (N*W)
+  int64_t stats_off;   // words into stats (nrb*(kmax+3))
+};
+
+// Work items: (set, a, b) packed as set << 40 | a << 20 | b.
+__host__ __device__ inline uint64_t pack_item(int64_t set, int64_t a, int64_t b) {
+  return ((uint64_t)set << 40) | ((uint64_t)a << 20) | (uint64_t)b;
+}
+__host__ __device__ inline void unpack_item(uint64_t it, int64_t* set, int64_t* a, int64_t* b) {
+  *set = (int64_t)(it >> 40);
+  *a = (int64_t)((it >> 20) & 0xFFFFF);
+  *b = (int64_t)(it & 0xFFFFF);
+}
+
+struct BatchDev {
+  int nsets;
+  const BatchSet* sets;
+  double* coords;
+  int64_t* orig;
+  SortRec* recs;
+  double* raw;
+  uint64_t* bits;
+  uint64_t* stats;
+  // item tables
+  const uint64_t* sort_items;  int64_t n_sort;     // (set, tile, 0)
+  const uint64_t* elem_items;  int64_t n_elem;     // (set, chunk of 256, 0)
+  const uint64_t* link_items;  int64_t n_link;     // (set, row tile, word tile)
+  const uint64_t* pop_items;   int64_t n_pop;      // (set, bi, bj), 64-row blocks
+  const uint64_t* mfma_items;  int64_t n_mfma;     // (set, BI, BJ), 256-row blocks
+  uint32_t* queue_heads;                           // [0] pop, [1] mfma
+  cs_result* results;
+  double c4;                                       // 4/sqrt(6), rounded once on the host
+};
+
+hipError_t launch_batch_sprinkle(const BatchDev& b, hipStream_t st);
+hipError_t launch_batch_link(const BatchDev& b, hipStream_t st);
+hipError_t launch_batch_count_pop(const BatchDev& b, int grid, hipStream_t st);
+hipError_t launch_batch_count_mfma(const BatchDev& b, int grid, hipStream_t st);
+hipError_t launch_batch_finish(const BatchDev& b, hipStream_t st);
+
 // BD action from abundances (host): exact int64 bracket, one rounding.
 double bd_action(int d, int64_t N, const uint64_t* n);
 

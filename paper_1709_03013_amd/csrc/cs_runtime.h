@@ -44,6 +44,7 @@ struct DevBuf {
 
 struct BatchState;
 struct QueueState;
+struct Tuner;
 
 }  // namespace cs
 
@@ -55,6 +56,7 @@ struct cs_ctx {
   cs::Pool pool;
   std::unique_ptr<cs::BatchState, void (*)(cs::BatchState*)> batch{nullptr, nullptr};
   std::unique_ptr<cs::QueueState, void (*)(cs::QueueState*)> queue{nullptr, nullptr};
+  std::unique_ptr<cs::Tuner, void (*)(cs::Tuner*)> tuner{nullptr, nullptr};
 };
 
 struct cs_set {
@@ -79,5 +81,9 @@ hipError_t run_count(const uint64_t* bits, int64_t N, int64_t W, int kmax, int p
 cs_status count_matrix(cs_ctx* ctx, const uint64_t* bits, int64_t N, int64_t W, int kmax,
                        int path, uint64_t* tot_host, uint64_t* rows_host, hipStream_t st);
 void destroy_batch_state(cs_ctx* ctx);
+void destroy_tuner(Tuner* t);
+Tuner* new_tuner();
+// Counting path for a set of d, N on this context (timed once per size bucket).
+int tuned_path(cs_ctx* ctx, int d, int64_t N);
 
 }  // namespace cs

@@ -2,15 +2,7 @@
 #include "cs_internal.h"
 #include "cs_runtime.h"
 
-namespace cs {
-void destroy_batch_state(cs_ctx* ctx) { (void)ctx; }
-}  // namespace cs
-
 extern "C" {
-cs_status cs_batch_run(cs_ctx* ctx, int nsets, const cs_req* reqs, cs_result* out) {
-  (void)ctx; (void)nsets; (void)reqs; (void)out;
-  return cs::fail(CS_EUNSUPPORTED, "cs_batch_run: not built yet");
-}
 cs_status cs_queue_start(cs_ctx* ctx, int slots, uint64_t resident_budget) {
   (void)ctx; (void)slots; (void)resident_budget;
   return cs::fail(CS_EUNSUPPORTED, "queue: not built yet");

@@ -65,23 +65,19 @@ __device__ __forceinline__ v4i spread4(uint32_t D, int r0) {
 
 // WM x WN waves over the 256x256 tile; each wave owns (256/WM) x (256/WN)
 // pairs as TM x TN tiles of 32x32.
+// One 256x256 tile of pairs (row block BI <= column block BJ) by one
+// workgroup.  lds_hist (FULL only) holds kmax+2 zeroed bins.
 template <int WM, int WN, bool FULL>
-__global__ __launch_bounds__(64 * WM * WN, 1) void k_count_mfma(
-    const uint64_t* __restrict__ bits, int64_t N, int64_t W, int64_t nb,
-    int kmax, uint64_t* __restrict__ rb_stats) {
+__device__ __forceinline__ void mfma_tile(const uint64_t* __restrict__ bits, int64_t N,
+                                          int64_t W, int64_t BI, int64_t BJ, int kmax,
+                                          uint64_t* __restrict__ rb_stats,
+                                          uint32_t* lds_hist) {
   constexpr int kThreads = 64 * WM * WN;
   constexpr int TM = kBT / WM / 32;
   constexpr int TN = kBT / WN / 32;
-  extern __shared__ uint32_t lds_hist[];  // FULL only: kmax+2 bins
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int r32 = lane & 31, g = lane >> 5;
-  int64_t BI, BJ;
-  tri_tile_longest_first((int64_t)blockIdx.x, nb, &BI, &BJ);
-  if constexpr (FULL) {
-    for (int b = tid; b <= kmax + 1; b += kThreads) lds_hist[b] = 0;
-    __syncthreads();
-  }
   const int64_t I0 = BI * kBT + (wave / WN) * (32 * TM);
   const int64_t J0 = BJ * kBT + (wave % WN) * (32 * TN);
 
@@ -237,6 +233,39 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void k_count_mfma(
   }
 }
 
+template <int WM, int WN, bool FULL>
+__global__ __launch_bounds__(64 * WM * WN, 1) void k_count_mfma(
+    const uint64_t* __restrict__ bits, int64_t N, int64_t W, int64_t nb,
+    int kmax, uint64_t* __restrict__ rb_stats) {
+  extern __shared__ uint32_t lds_hist[];  // FULL only: kmax+2 bins
+  int64_t BI, BJ;
+  tri_tile_longest_first((int64_t)blockIdx.x, nb, &BI, &BJ);
+  if constexpr (FULL) {
+    for (int b = threadIdx.x; b <= kmax + 1; b += 64 * WM * WN) lds_hist[b] = 0;
+    __syncthreads();
+  }
+  mfma_tile<WM, WN, FULL>(bits, N, W, BI, BJ, kmax, rb_stats, lds_hist);
+}
+
+// Batched, persistent: each workgroup takes (set, BI, BJ) items from a device
+// queue (longest first) until it is empty.
+__global__ __launch_bounds__(512, 1) void k_batch_count_mfma(BatchDev b) {
+  __shared__ uint32_t item_sh;
+  for (;;) {
+    const uint32_t mine = next_item(&b.queue_heads[1]);
+    if (threadIdx.x == 0) item_sh = mine;
+    __syncthreads();
+    const uint32_t it = __builtin_amdgcn_readfirstlane(item_sh);
+    __syncthreads();
+    if ((int64_t)it >= b.n_mfma) break;
+    int64_t set, BI, BJ;
+    unpack_item(b.mfma_items[it], &set, &BI, &BJ);
+    const BatchSet bs = b.sets[set];
+    mfma_tile<2, 4, false>(b.bits + bs.bits_off, bs.N, bs.W, BI, BJ, 3, b.stats + bs.stats_off,
+                           nullptr);
+  }
+}
+
 template <int WM, int WN>
 hipError_t launch_variant(const uint64_t* bits, int64_t N, int64_t W, int kmax,
                           uint64_t* rb_stats, hipStream_t st) {
@@ -273,6 +302,12 @@ hipError_t launch_count_mfma(const uint64_t* bits, int64_t N, int64_t W, int kma
   if (N <= 1) return hipSuccess;
   if (mfma_variant() == 1) return launch_variant<2, 4>(bits, N, W, kmax, rb_stats, st);
   return launch_variant<2, 2>(bits, N, W, kmax, rb_stats, st);
+}
+
+hipError_t launch_batch_count_mfma(const BatchDev& b, int grid, hipStream_t st) {
+  if (b.n_mfma <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_count_mfma, dim3((unsigned)grid), dim3(512), 0, st, b);
+  return hipGetLastError();
 }
 
 }  // namespace cs

@@ -27,22 +27,17 @@ namespace {
 
 constexpr int kChunk = 4;  // words per staging step (rows are 4-word aligned)
 
+// One 64x64 tile of pairs (rows of block bi against rows of block bj >= bi)
+// by one 64-lane workgroup.  sI, sJ: word-major staging, sI[k][r] = word
+// (w+k) of row 64bi+r.  lds_hist (FULL only) holds kmax+1 zeroed bins.
 template <bool FULL>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_count_pop(
-    const uint64_t* __restrict__ bits, int64_t N, int64_t W, int64_t nb,
-    int kmax, uint64_t* __restrict__ rb_stats) {
-  // word-major staging: sI[k][r] = word (w+k) of row 64bi+r, same for sJ
-  __shared__ uint64_t sI[kChunk][64];
-  __shared__ uint64_t sJ[kChunk][64];
-  extern __shared__ uint32_t lds_hist[];  // FULL only: kmax+1 bins
+__device__ __forceinline__ void pop_tile(const uint64_t* __restrict__ bits, int64_t N,
+                                         int64_t W, int64_t bi, int64_t bj, int kmax,
+                                         uint64_t* __restrict__ rb_stats,
+                                         uint32_t* lds_hist, uint64_t (*sI)[64],
+                                         uint64_t (*sJ)[64]) {
   const int lane = threadIdx.x;
   const int li = lane >> 3, lj = lane & 7;
-  int64_t bi, bj;
-  tri_tile_longest_first((int64_t)blockIdx.x, nb, &bi, &bj);
-
-  if constexpr (FULL) {
-    for (int b = lane; b <= kmax; b += 64) lds_hist[b] = 0;
-  }
 
   // Staging rows of this lane: I row 64bi+lane and J row 64bj+lane.
   const int64_t ri = bi * 64 + lane, rj = bj * 64 + lane;
@@ -150,6 +145,76 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
   }
 }
 
+template <bool FULL>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_count_pop(
+    const uint64_t* __restrict__ bits, int64_t N, int64_t W, int64_t nb,
+    int kmax, uint64_t* __restrict__ rb_stats) {
+  __shared__ uint64_t sI[kChunk][64];
+  __shared__ uint64_t sJ[kChunk][64];
+  extern __shared__ uint32_t lds_hist[];  // FULL only: kmax+1 bins
+  int64_t bi, bj;
+  tri_tile_longest_first((int64_t)blockIdx.x, nb, &bi, &bj);
+  if constexpr (FULL) {
+    for (int b = threadIdx.x; b <= kmax; b += 64) lds_hist[b] = 0;
+  }
+  pop_tile<FULL>(bits, N, W, bi, bj, kmax, rb_stats, lds_hist, sI, sJ);
+}
+
+// Batched, persistent: each 64-lane workgroup takes (set, bi, bj) items from
+// a device queue (longest first) until it is empty.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_batch_count_pop(
+    BatchDev b) {
+  __shared__ uint64_t sI[kChunk][64];
+  __shared__ uint64_t sJ[kChunk][64];
+  for (;;) {
+    const uint32_t it = next_item(&b.queue_heads[0]);
+    if ((int64_t)it >= b.n_pop) break;
+    int64_t set, bi, bj;
+    unpack_item(b.pop_items[it], &set, &bi, &bj);
+    const BatchSet bs = b.sets[set];
+    pop_tile<false>(b.bits + bs.bits_off, bs.N, bs.W, bi, bj, 3, b.stats + bs.stats_off,
+                    nullptr, sI, sJ);
+  }
+}
+
+// Batched epilogue: one workgroup per set sums its row-block stats and
+// evaluates the BD action (same integer bracket and single rounding as the
+// single-set path).
+__global__ __launch_bounds__(256) void k_batch_finish(BatchDev b) {
+  __shared__ uint64_t part[6][256];
+  const int s = blockIdx.x;
+  const BatchSet bs = b.sets[s];
+  const int64_t nrb = (bs.N + kRowBlock - 1) / kRowBlock;
+  uint64_t acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t r = threadIdx.x; r < nrb; r += 256)
+    for (int c = 0; c < 6; ++c) acc[c] += b.stats[bs.stats_off + r * 6 + c];
+  for (int c = 0; c < 6; ++c) part[c][threadIdx.x] = acc[c];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+      for (int c = 0; c < 6; ++c) part[c][threadIdx.x] += part[c][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    cs_result r;
+    for (int c = 0; c < 4; ++c) r.n[c] = part[c][0];
+    r.R = part[4][0];
+    r.summ = part[5][0];
+    const int64_t N = bs.N;
+    if (bs.d == 2) {
+      const int64_t K = N - 2 * (int64_t)r.n[0] + 4 * (int64_t)r.n[1] - 2 * (int64_t)r.n[2];
+      r.S = 2.0 * (double)K;
+    } else {
+      const int64_t K = N - (int64_t)r.n[0] + 9 * (int64_t)r.n[1] - 16 * (int64_t)r.n[2] +
+                        8 * (int64_t)r.n[3];
+      r.S = b.c4 * (double)K;
+    }
+    r.status = CS_OK;
+    r.reserved = 0;
+    b.results[s] = r;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_reduce_rows(
     const uint64_t* __restrict__ rb, int64_t nrb, int stride,
     uint64_t* __restrict__ tot) {
@@ -184,6 +249,18 @@ hipError_t launch_count_pop(const uint64_t* bits, int64_t N, int64_t W,
     hipLaunchKernelGGL(k_count_pop<true>, dim3((unsigned)ntiles), dim3(64), lds, st,
                        bits, N, W, nb, kmax, rb_stats);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_count_pop(const BatchDev& b, int grid, hipStream_t st) {
+  if (b.n_pop <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_count_pop, dim3((unsigned)grid), dim3(64), 0, st, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_finish(const BatchDev& b, hipStream_t st) {
+  if (b.nsets <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_finish, dim3((unsigned)b.nsets), dim3(256), 0, st, b);
   return hipGetLastError();
 }
 

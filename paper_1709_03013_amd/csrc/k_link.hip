@@ -43,16 +43,14 @@ __device__ __forceinline__ bool related_sym(const Pt<D>& a, const Pt<D>& b) {
   }
 }
 
+// One 64-row x 64-word tile of the matrix, rows i0.., words w0.. (256 threads).
 template <int D>
-__global__ __launch_bounds__(256) void k_link(const double* __restrict__ coords,
-                                              int64_t N,
-                                              uint64_t* __restrict__ bits,
-                                              int64_t W) {
-  __shared__ uint64_t tile[64][65];
+__device__ __forceinline__ void link_tile(const double* __restrict__ coords, int64_t N,
+                                          uint64_t* __restrict__ bits, int64_t W,
+                                          int64_t i0, int64_t w0,
+                                          uint64_t (*tile)[65]) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int64_t i0 = (int64_t)blockIdx.y * 64;
-  const int64_t w0 = (int64_t)blockIdx.x * 64;
   const int64_t rem = N - i0;
   const int nrows = rem < 64 ? (int)rem : 64;
   for (int wl = 0; wl < 16; ++wl) {
@@ -85,6 +83,27 @@ __global__ __launch_bounds__(256) void k_link(const double* __restrict__ coords,
     const int64_t w = w0 + lane;
     if (i < N && w < W) bits[i * W + w] = tile[r][lane];
   }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_link(const double* __restrict__ coords,
+                                              int64_t N,
+                                              uint64_t* __restrict__ bits,
+                                              int64_t W) {
+  __shared__ uint64_t tile[64][65];
+  link_tile<D>(coords, N, bits, W, (int64_t)blockIdx.y * 64, (int64_t)blockIdx.x * 64, tile);
+}
+
+// Batched: one workgroup per (set, 64-row tile, 64-word tile) item.
+__global__ __launch_bounds__(256) void k_batch_link(BatchDev b) {
+  __shared__ uint64_t tile[64][65];
+  int64_t set, ti, tw;
+  unpack_item(b.link_items[blockIdx.x], &set, &ti, &tw);
+  const BatchSet bs = b.sets[set];
+  if (bs.d == 2)
+    link_tile<2>(b.coords + bs.coords_off, bs.N, b.bits + bs.bits_off, bs.W, ti * 64, tw * 64, tile);
+  else
+    link_tile<4>(b.coords + bs.coords_off, bs.N, b.bits + bs.bits_off, bs.W, ti * 64, tw * 64, tile);
 }
 
 __global__ __launch_bounds__(256) void k_fill_u64(uint64_t* __restrict__ p,
@@ -130,6 +149,12 @@ hipError_t launch_link(int d, int64_t N, const double* coords, uint64_t* bits,
     hipLaunchKernelGGL(k_link<2>, grid, dim3(256), 0, st, coords, N, bits, W);
   else
     hipLaunchKernelGGL(k_link<4>, grid, dim3(256), 0, st, coords, N, bits, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_link(const BatchDev& b, hipStream_t st) {
+  if (b.n_link <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_link, dim3((unsigned)b.n_link), dim3(256), 0, st, b);
   return hipGetLastError();
 }
 

@@ -164,15 +164,13 @@ __device__ __forceinline__ bool rec_less(const SortRec& a, const SortRec& b) {
   return a.idx < b.idx;
 }
 
-__global__ __launch_bounds__(1024) void k_tile_sort(SortRec* __restrict__ recs,
-                                                    int64_t N) {
-  __shared__ SortRec s[kSortTile];
+// Bitonic sort of n <= kSortTile records at base, in LDS, by 1024 threads.
+__device__ __forceinline__ void tile_sort_body(SortRec* __restrict__ base, int64_t n,
+                                               SortRec* s) {
   const int tid = threadIdx.x;
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
-  const int64_t n = N - base < kSortTile ? N - base : kSortTile;
   for (int q = tid; q < kSortTile; q += 1024) {
     if (q < n) {
-      s[q] = recs[base + q];
+      s[q] = base[q];
     } else {
       s[q].k1 = ~0ull;
       s[q].k2 = ~0ull;
@@ -196,15 +194,25 @@ __global__ __launch_bounds__(1024) void k_tile_sort(SortRec* __restrict__ recs,
       __syncthreads();
     }
   }
-  for (int q = tid; q < n; q += 1024) recs[base + q] = s[q];
+  for (int q = tid; q < n; q += 1024) base[q] = s[q];
 }
 
+__global__ __launch_bounds__(1024) void k_tile_sort(SortRec* __restrict__ recs,
+                                                    int64_t N) {
+  __shared__ SortRec s[kSortTile];
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  const int64_t n = N - base < kSortTile ? N - base : kSortTile;
+  tile_sort_body(recs + base, n, s);
+}
+
+// Final position of record e of a set: its rank in its own sorted tile plus
+// the number of smaller records in every other tile; scatter its
+// coordinates there.
 template <int D>
-__global__ __launch_bounds__(256) void k_rank_scatter(
-    const SortRec* __restrict__ recs, int64_t N, const double* __restrict__ raw,
-    double* __restrict__ coords, int64_t* __restrict__ orig) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= N) return;
+__device__ __forceinline__ void rank_scatter_one(const SortRec* __restrict__ recs,
+                                                 int64_t N, const double* __restrict__ raw,
+                                                 double* __restrict__ coords,
+                                                 int64_t* __restrict__ orig, int64_t e) {
   const SortRec my = recs[e];
   if (my.idx >= (uint64_t)N) return;  // unfilled record (too few 4D draws)
   const int64_t mytile = e / kSortTile;
@@ -232,6 +240,14 @@ __global__ __launch_bounds__(256) void k_rank_scatter(
   }
 }
 
+template <int D>
+__global__ __launch_bounds__(256) void k_rank_scatter(
+    const SortRec* __restrict__ recs, int64_t N, const double* __restrict__ raw,
+    double* __restrict__ coords, int64_t* __restrict__ orig) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < N) rank_scatter_one<D>(recs, N, raw, coords, orig, e);
+}
+
 __global__ __launch_bounds__(256) void k_fill_recs(SortRec* __restrict__ recs,
                                                    int64_t n) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -240,6 +256,91 @@ __global__ __launch_bounds__(256) void k_fill_recs(SortRec* __restrict__ recs,
     recs[e].k2 = ~0ull;
     recs[e].idx = ~0ull;
   }
+}
+
+// ---- batched ensembles ------------------------------------------------------
+// One workgroup draws one whole set.  In 4D it walks the candidates 256 at a
+// time, ranks the accepted ones with wave ballots and stops, all lanes
+// together, as soon as N are accepted: the same first N accepted candidates,
+// in candidate order, as the single-set path.
+__global__ __launch_bounds__(256) void k_batch_sprinkle(BatchDev b) {
+  __shared__ uint32_t wcnt[4];
+  const BatchSet bs = b.sets[blockIdx.x];
+  const int64_t N = bs.N;
+  if (N <= 0) return;
+  SortRec* recs = b.recs + bs.rec_off;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (bs.d == 2) {
+    for (int64_t c = tid; c < N; c += 256) {
+      uint64_t r[4] = {(uint64_t)c, 0, 0, 0};
+      philox10(r, bs.seed, 1);
+      const uint64_t a = r[0] >> 11, bb = r[1] >> 11;
+      SortRec s;
+      s.k1 = a + bb;
+      s.k2 = a;
+      s.idx = (uint64_t)c;
+      recs[c] = s;
+    }
+    return;
+  }
+  double* raw = b.raw + bs.raw_off;
+  int64_t accepted = 0;
+  for (int64_t base = 0; accepted < N; base += 256) {
+    const int64_t c = base + tid;
+    double xyz[4];
+    uint64_t kt = 0;
+    const bool acc = candidate4d((uint64_t)c, bs.seed, xyz, &kt);
+    const uint64_t bal = __ballot(acc);
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+        (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+    if (lane == 0) wcnt[wave] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    uint32_t woff = 0, tot = 0;
+    for (int q = 0; q < 4; ++q) {
+      woff += q < wave ? wcnt[q] : 0u;
+      tot += wcnt[q];
+    }
+    // the same for every lane: keep the loop exit a scalar branch
+    tot = __builtin_amdgcn_readfirstlane(tot);
+    const int64_t e = accepted + woff + below;
+    if (acc && e < N) {
+      SortRec s;
+      s.k1 = kt;
+      s.k2 = 0;
+      s.idx = (uint64_t)e;
+      recs[e] = s;
+      raw[e] = xyz[0];
+      raw[N + e] = xyz[1];
+      raw[2 * N + e] = xyz[2];
+      raw[3 * N + e] = xyz[3];
+    }
+    accepted += tot;
+    __syncthreads();  // wcnt is rewritten next round
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_batch_tile_sort(BatchDev b) {
+  __shared__ SortRec s[kSortTile];
+  int64_t set, tile, unused;
+  unpack_item(b.sort_items[blockIdx.x], &set, &tile, &unused);
+  const BatchSet bs = b.sets[set];
+  const int64_t base = tile * kSortTile;
+  const int64_t n = bs.N - base < kSortTile ? bs.N - base : kSortTile;
+  tile_sort_body(b.recs + bs.rec_off + base, n, s);
+}
+
+__global__ __launch_bounds__(256) void k_batch_rank_scatter(BatchDev b) {
+  int64_t set, chunk, unused;
+  unpack_item(b.elem_items[blockIdx.x], &set, &chunk, &unused);
+  const BatchSet bs = b.sets[set];
+  const int64_t e = chunk * 256 + threadIdx.x;
+  if (e >= bs.N) return;
+  if (bs.d == 2)
+    rank_scatter_one<2>(b.recs + bs.rec_off, bs.N, nullptr, b.coords + bs.coords_off,
+                        b.orig + bs.orig_off, e);
+  else
+    rank_scatter_one<4>(b.recs + bs.rec_off, bs.N, b.raw + bs.raw_off,
+                        b.coords + bs.coords_off, b.orig + bs.orig_off, e);
 }
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -299,6 +400,16 @@ hipError_t launch_sprinkle(int d, int64_t N, uint64_t seed, int64_t ncand,
   else
     hipLaunchKernelGGL(k_rank_scatter<4>, dim3(gN), dim3(256), 0, st, recs, N,
                        raw, coords, orig);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_sprinkle(const BatchDev& b, hipStream_t st) {
+  if (b.nsets <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_sprinkle, dim3((unsigned)b.nsets), dim3(256), 0, st, b);
+  if (b.n_sort > 0)
+    hipLaunchKernelGGL(k_batch_tile_sort, dim3((unsigned)b.n_sort), dim3(1024), 0, st, b);
+  if (b.n_elem > 0)
+    hipLaunchKernelGGL(k_batch_rank_scatter, dim3((unsigned)b.n_elem), dim3(256), 0, st, b);
   return hipGetLastError();
 }
 
