@@ -148,6 +148,57 @@ def ensemble(cs, ctx, nsets=512):
     return out
 
 
+def served(cs, nreq=10000, slots=4, budget_gib=32, load=0.7):
+    """Served stream: requests with Poisson arrivals (N log-uniform in
+    [512, 32768], d in {2, 4}).  The saturated rate is measured first on a
+    burst of the first 1500 requests; the timed run offers all requests at
+    `load` times that rate."""
+    import causet_inputs as ci
+    plan = ci.request_plan(nreq)
+    ctx = cs.cs_create(0, int(budget_gib * 2**30), None)
+    try:
+        cs.cs_queue_start(ctx, slots, int(budget_gib * 2**30 / 2))
+
+        def drive(reqs, arrivals):
+            t0 = time.perf_counter()
+            pending = {}
+            lat = []
+            k = 0
+            done = 0
+            while done < len(reqs):
+                now = time.perf_counter() - t0
+                while k < len(reqs) and (arrivals is None or arrivals[k] <= now):
+                    d, N, seed = reqs[k]
+                    pending[cs.cs_queue_submit(ctx, d, N, seed)] = k
+                    k += 1
+                for t in list(pending):
+                    r = cs.cs_queue_poll(ctx, t)
+                    if r is not None:
+                        res, tm = r
+                        assert res["status"] == 0
+                        lat.append(tm[2])
+                        del pending[t]
+                        done += 1
+                if k < len(reqs) and arrivals is not None:
+                    time.sleep(max(0.0, min(0.0005, arrivals[k] - (time.perf_counter() - t0))))
+            return time.perf_counter() - t0, np.array(lat)
+
+        reqs = [(d, N, seed) for _, d, N, seed in plan]
+        cal_n = min(1500, nreq)
+        t_cal, _ = drive(reqs[:cal_n], None)
+        sat = cal_n / t_cal
+        rate = load * sat
+        gaps = np.array([a for a, *_ in plan])
+        gaps = gaps / gaps[-1] * (nreq / rate)  # rescale the Poisson arrivals to `rate`
+        t_run, lat = drive(reqs, gaps)
+        return {"requests": nreq, "slots": slots, "hbm_budget_gib": budget_gib,
+                "saturated_actions_per_s": sat, "offered_rate_per_s": rate,
+                "actions_per_s": nreq / t_run, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3), "wall_s": t_run}
+    finally:
+        cs.cs_destroy(ctx)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +208,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-span", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=10000)
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -212,6 +265,7 @@ def main():
     cs.cs_set_free(s)
 
     ens = None if a.no_batch else ensemble(cs, ctx)
+    srv = None if a.no_serve else served(cs, a.serve_requests)
     cpu = None if a.no_cpu else cpu_baseline()
     cs.cs_destroy(ctx)
 
@@ -228,6 +282,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "ensemble": ens,
+        "served": srv,
     }
     print(json.dumps(rec))
 

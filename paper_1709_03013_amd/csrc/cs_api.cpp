@@ -253,7 +253,16 @@ cs_status cs_sprinkle(cs_ctx* ctx, int d, int64_t N, uint64_t seed, cs_set** out
       cs_set_free(s);
       return hip_fail(e, "sprinkle launch");
     }
-    if (d == 2) break;
+    if (d == 2) {
+      // finish before the scratch returns to the pool: another stream (a
+      // queue slot) may be handed the same block next
+      e = hipStreamSynchronize(ctx->stream);
+      if (e != hipSuccess) {
+        cs_set_free(s);
+        return hip_fail(e, "sprinkle");
+      }
+      break;
+    }
     uint64_t got = 0;
     e = hipMemcpyAsync(&got, acc.p, 8, hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
