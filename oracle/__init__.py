@@ -81,6 +81,8 @@ def lib() -> ctypes.CDLL:
         L.orc_three_chains.restype = ctypes.c_uint64
         L.orc_bd_action.argtypes = [ctypes.c_int, ctypes.c_int64, _u64p]
         L.orc_bd_action.restype = ctypes.c_double
+        L.orc_smeared_action.argtypes = [ctypes.c_int64, _u64p, ctypes.c_int64, ctypes.c_double]
+        L.orc_smeared_action.restype = ctypes.c_double
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = ctypes.c_int
         _lib = L
@@ -177,6 +179,12 @@ def bd_action(d: int, N: int, n) -> float:
     if a.size < 4:
         a = np.concatenate([a, np.zeros(4 - a.size, dtype=np.uint64)])
     return float(lib().orc_bd_action(d, N, _p(a, _u64p)))
+
+
+def smeared_action(N: int, hist, eps: float) -> float:
+    """Eq. 5 from the full histogram hist[k] = N_k (k = 0..len-1)."""
+    h = np.ascontiguousarray(np.asarray(hist, dtype=np.uint64))
+    return float(lib().orc_smeared_action(N, _p(h, _u64p), h.size, eps))
 
 
 def num_threads() -> int:

@@ -348,6 +348,31 @@ double orc_bd_action(int d, int64_t N, const uint64_t* n) {
   return NAN;
 }
 
+/* Smeared BD action, Eq. 5 (2D):
+ *   S_eps = 2 eps [ N - 2 eps sum_{i=1}^{N-1} n_i f2(i-1, eps) ]
+ *   f2(k, eps) = (1-eps)^k [1 - 2 eps k/(1-eps) + eps^2 k(k-1) / (2 (1-eps)^2)]
+ * with n_i = N_{i-1} (hist[k] = N_k, k = 0..nbins-1).  f2 is evaluated in the
+ * algebraically equal form without division,
+ *   f2(k) = q^k - 2 eps k q^(k-1) + eps^2 (k(k-1)/2) q^(k-2),  q = 1 - eps,
+ * which is defined at eps = 1 (where Eq. 5 reduces to Eq. 4).  Evaluation
+ * order (a reading the paper leaves open): q^k by repeated multiplication
+ * from q^0 = 1; terms in the order written; the sum over k ascending. */
+double orc_smeared_action(int64_t N, const uint64_t* hist, int64_t nbins, double eps) {
+  const double q = 1.0 - eps;
+  double pk = 1.0, pk1 = 0.0, pk2 = 0.0; /* q^k, q^(k-1), q^(k-2) */
+  double sum = 0.0;
+  for (int64_t k = 0; k < nbins; ++k) {
+    const double twoek = (2.0 * eps) * (double)k;
+    const double c = (double)(k * (k - 1) / 2);
+    const double f = (pk - twoek * pk1) + ((eps * eps) * c) * pk2;
+    sum = sum + (double)hist[k] * f;
+    pk2 = pk1;
+    pk1 = pk;
+    pk = pk * q;
+  }
+  return (2.0 * eps) * ((double)N - (2.0 * eps) * sum);
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();
