@@ -34,6 +34,7 @@ sys.path.insert(0, ROOT)
 WORKLOAD = dict(d=2, N=131072, seed=3)
 PEAK = {
     "int8_mfma_tops": 5.0e15,      # dense int8 MFMA, ops/s
+    "fp4_mfma_flops": 10.1e15,     # dense fp4 MFMA, flop/s
     "alu_int32_ops": 256 * 64 * 2.4e9,  # 256 CU x 64 lanes x 2.4 GHz, 32-bit VALU ops/s
     "hbm_bytes": 8.0e12,
 }
@@ -209,6 +210,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-span", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES between two device buffers 3 times (calibrates HBM counters)")
     ap.add_argument("--serve-requests", type=int, default=10000)
     a = ap.parse_args()
     if a.gpus != 1:
@@ -217,6 +220,19 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if a.copy_probe:
+        # a plain device-to-device copy of known size: what FETCH_SIZE and
+        # WRITE_SIZE read for it calibrates those counters for the count kernel
+        n = a.copy_probe // 8
+        src = torch.arange(n, dtype=torch.int64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 8, "copies": 3}))
+        return
+
     import paper_1709_03013_amd as cs
 
     torch.cuda.init()
@@ -242,12 +258,16 @@ def main():
     log("step %.1f ms, count %s ms" % (ms_step, ["%.1f" % x for x in count_ms]))
 
     N = WORKLOAD["N"]
-    path_used = a.path if a.path else (2 if N >= 2048 else 1)
+    path_used = cs.cs_set_count_path(s)
     t_count = float(np.mean(count_ms)) / 1000.0
-    if path_used == 2:
+    if path_used in (2, 3):
         ops = 2.0 * math.comb(N, 3)
-        roof = {"bound": "mfma", "achieved": ops / t_count / 1e12, "peak": PEAK["int8_mfma_tops"] / 1e12,
-                "unit": "TFLOP/s", "kernel": "k_count_mfma", "work": "2*C(N,3) int8 ops (one MAC per triple i<k<j)"}
+        fp4 = path_used == 3
+        roof = {"bound": "mfma", "achieved": ops / t_count / 1e12,
+                "peak": (PEAK["fp4_mfma_flops"] if fp4 else PEAK["int8_mfma_tops"]) / 1e12,
+                "unit": "TFLOP/s" if fp4 else "TOP/s",
+                "kernel": "k_count_mfma<fp4>" if fp4 else "k_count_mfma<int8>",
+                "work": "2*C(N,3) ops (one multiply-add per triple i<k<j), %s operands" % ("fp4 e2m1 0/1" if fp4 else "int8 0/1")}
     else:
         if a.no_span:
             walg = None
@@ -275,10 +295,10 @@ def main():
         "unit": "interval pairs/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u64", "data": "synthetic",
+        "dtype": {1: "u32", 2: "i8", 3: "fp4"}[path_used], "data": "synthetic",
         "config": {"workload": "2D flat causal diamond, N=131072, seed 3 (sprinkle+sort+link+count+action)",
                    "N": N, "d": 2, "related_pairs": R, "abundances": [int(x) for x in n],
-                   "action": S, "count_path": {1: "pop", 2: "mfma"}[path_used]},
+                   "action": S, "count_path": {1: "pop", 2: "mfma_int8", 3: "mfma_fp4"}[path_used]},
         "roofline": roof,
         "cpu_baseline": cpu,
         "ensemble": ens,

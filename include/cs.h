@@ -51,9 +51,11 @@ typedef enum {
 } cs_status;
 
 enum {
-  CS_PATH_AUTO = 0,     /* library picks POP or MFMA from density and size */
+  CS_PATH_AUTO = 0,     /* library picks the fastest path for the size (timed once) */
   CS_PATH_POP = 1,      /* VALU AND + popcount kernel */
-  CS_PATH_MFMA = 2      /* int8 MFMA contraction (future x past) kernel */
+  CS_PATH_MFMA = 2,     /* int8 MFMA contraction (future x past), int32 sums */
+  CS_PATH_MFMA_FP4 = 3  /* the same contraction with FP4 (e2m1) 0/1 operands and
+                           exact fp32 sums (m < 2^24); N must be below 2^24 */
 };
 
 typedef struct cs_ctx cs_ctx;
@@ -117,6 +119,9 @@ cs_status cs_get_bitset(cs_ctx* ctx, const cs_set* set, uint64_t* rows);
 /* Device pointer of the packed matrix (N*W words), NULL if not linked.
  * Valid until cs_set_free. */
 const uint64_t* cs_set_bitset_dev(const cs_set* set);
+/* Count path (CS_PATH_POP / MFMA / MFMA_FP4) used by the set's last
+ * cs_interval_abundances call (what CS_PATH_AUTO resolved to); 0 if none. */
+int cs_set_count_path(const cs_set* set);
 
 /* ------------------------------------------------------------------- link */
 /* Build the packed causal matrix from the set's coordinates (Sec. 2.2):
@@ -128,9 +133,11 @@ cs_status cs_link(cs_ctx* ctx, cs_set* set);
 /* Interval abundances of a linked set.  out[0..kmax] receives N_0..N_kmax
  * (host memory, caller-owned, kmax+1 entries, kmax >= 3); R_out the number
  * of related pairs, summ_out the sum of interior counts over related pairs
- * (either may be NULL).  path: CS_PATH_AUTO / POP / MFMA; the result does not
- * depend on it.  kmax is at most CS_KMAX_MAX. */
-#define CS_KMAX_MAX 4095
+ * (either may be NULL).  path: CS_PATH_AUTO / POP / MFMA / MFMA_FP4; the
+ * result does not depend on it.  kmax is at most CS_KMAX_MAX; kmax = N-2
+ * gives the full histogram (bins beyond 8191 are added to device memory with
+ * atomics, so very large kmax is slower than kmax = 3). */
+#define CS_KMAX_MAX 16777213
 cs_status cs_interval_abundances(cs_ctx* ctx, cs_set* set, int kmax,
                                  uint64_t* out, uint64_t* R_out,
                                  uint64_t* summ_out, int path);
@@ -153,6 +160,15 @@ cs_status cs_interval_abundances_rows(cs_ctx* ctx, cs_set* set, int kmax,
  * Counts the set (path AUTO) if it has not been counted yet.  CS_EINVAL if
  * the set has d = 0. */
 cs_status cs_bd_action(cs_ctx* ctx, cs_set* set, double* S_out);
+
+/* Smeared (non-local) BD action S_eps of Eq. 5, a 2D quantity (set d = 2):
+ *   S_eps = 2 eps [N - 2 eps sum_k N_k f2(k, eps)],
+ *   f2(k, eps) = q^k - 2 eps k q^(k-1) + eps^2 (k(k-1)/2) q^(k-2), q = 1-eps
+ * (Eq. 5's f2 with the division by 1-eps multiplied out, so eps = 1 gives
+ * Eq. 4 exactly).  Counts the full histogram N_0..N_{N-2} exactly on the
+ * device, then sums on the host in a fixed order: q^k by repeated
+ * multiplication, k ascending.  0 < eps <= 1, else CS_EINVAL. */
+cs_status cs_smeared_action(cs_ctx* ctx, cs_set* set, double eps, double* S_out);
 
 /* ----------------------------------------------------- device-pointer tier */
 /* The caller owns all memory and the stream; calls are asynchronous on

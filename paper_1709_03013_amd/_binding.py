@@ -16,9 +16,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcs_gfx950.so")
 
 CS_OK, CS_EINVAL, CS_ENOMEM, CS_EDEVICE, CS_EBUSY, CS_EUNSUPPORTED = range(6)
-PATH_AUTO, PATH_POP, PATH_MFMA = 0, 1, 2
+PATH_AUTO, PATH_POP, PATH_MFMA, PATH_MFMA_FP4 = 0, 1, 2, 3
 ROW_BLOCK = 256
-KMAX_MAX = 4095
+KMAX_MAX = 16777213
 STATUS_NAMES = {0: "CS_OK", 1: "CS_EINVAL", 2: "CS_ENOMEM", 3: "CS_EDEVICE",
                 4: "CS_EBUSY", 5: "CS_EUNSUPPORTED"}
 
@@ -64,10 +64,12 @@ _SIGS = {
     "cs_get_coords": (ctypes.c_int, [_vp, _vp, _dp, _i64p]),
     "cs_get_bitset": (ctypes.c_int, [_vp, _vp, _u64p]),
     "cs_set_bitset_dev": (_vp, [_vp]),
+    "cs_set_count_path": (ctypes.c_int, [_vp]),
     "cs_link": (ctypes.c_int, [_vp, _vp]),
     "cs_interval_abundances": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _u64p, _u64p, _u64p, ctypes.c_int]),
     "cs_interval_abundances_rows": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _u64p, ctypes.c_int]),
     "cs_bd_action": (ctypes.c_int, [_vp, _vp, _dp]),
+    "cs_smeared_action": (ctypes.c_int, [_vp, _vp, ctypes.c_double, _dp]),
     "cs_link_dev": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp]),
     "cs_count_workspace_bytes": (ctypes.c_uint64, [ctypes.c_int64, ctypes.c_int]),
     "cs_count_dev": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, _vp, _vp,
@@ -202,6 +204,10 @@ def cs_set_bitset_dev(s: int) -> int:
     return int(lib().cs_set_bitset_dev(s) or 0)
 
 
+def cs_set_count_path(s: int) -> int:
+    return int(lib().cs_set_count_path(s))
+
+
 def cs_link(ctx: int, s: int) -> None:
     _check(lib().cs_link(ctx, s))
 
@@ -226,6 +232,12 @@ def cs_interval_abundances_rows(ctx: int, s: int, kmax: int = 3, path: int = PAT
 def cs_bd_action(ctx: int, s: int) -> float:
     S = ctypes.c_double()
     _check(lib().cs_bd_action(ctx, s, ctypes.byref(S)))
+    return S.value
+
+
+def cs_smeared_action(ctx: int, s: int, eps: float) -> float:
+    S = ctypes.c_double()
+    _check(lib().cs_smeared_action(ctx, s, eps, ctypes.byref(S)))
     return S.value
 
 

@@ -2,6 +2,7 @@
 // path (sprinkle -> link -> count -> action) and the device-pointer tier.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -41,6 +42,24 @@ double bd_action(int d, int64_t N, const uint64_t* n) {
                     8 * (int64_t)n[3];
   const double c = 4.0 / std::sqrt(6.0);
   return c * (double)K;
+}
+
+double smeared_action(int64_t N, const uint64_t* hist, int64_t nbins, double eps) {
+  // f2(k) = q^k - 2 eps k q^(k-1) + eps^2 (k(k-1)/2) q^(k-2), summed over k
+  // ascending with q^k carried by repeated multiplication (Eq. 5).
+  const double q = 1.0 - eps;
+  double pk = 1.0, pk1 = 0.0, pk2 = 0.0;
+  double sum = 0.0;
+  for (int64_t k = 0; k < nbins; ++k) {
+    const double twoek = (2.0 * eps) * (double)k;
+    const double c = (double)(k * (k - 1) / 2);
+    const double f = (pk - twoek * pk1) + ((eps * eps) * c) * pk2;
+    sum = sum + (double)hist[k] * f;
+    pk2 = pk1;
+    pk1 = pk;
+    pk = pk * q;
+  }
+  return (2.0 * eps) * ((double)N - (2.0 * eps) * sum);
 }
 
 int choose_path(int64_t N, int kmax) {
@@ -145,6 +164,7 @@ hipError_t run_count(const uint64_t* bits, int64_t N, int64_t W, int kmax, int p
                      uint64_t* rb_stats, hipStream_t st) {
   if (path == CS_PATH_AUTO) path = choose_path(N, kmax);
   if (path == CS_PATH_MFMA) return launch_count_mfma(bits, N, W, kmax, rb_stats, st);
+  if (path == CS_PATH_MFMA_FP4) return launch_count_mfma_fp4(bits, N, W, kmax, rb_stats, st);
   return launch_count_pop(bits, N, W, kmax, rb_stats, st);
 }
 
@@ -404,6 +424,8 @@ cs_status cs_get_bitset(cs_ctx* ctx, const cs_set* s, uint64_t* rows) {
 
 const uint64_t* cs_set_bitset_dev(const cs_set* s) { return s && s->linked ? s->bits : nullptr; }
 
+int cs_set_count_path(const cs_set* s) { return s ? s->last_path : 0; }
+
 cs_status cs_link(cs_ctx* ctx, cs_set* s) {
   if (!ctx || !s) return fail(CS_EINVAL, "cs_link: NULL argument");
   if (s->linked) return CS_OK;
@@ -425,7 +447,9 @@ cs_status cs_link(cs_ctx* ctx, cs_set* s) {
 static cs_status check_count_args(cs_ctx* ctx, cs_set* s, int kmax, int path) {
   if (!ctx || !s) return fail(CS_EINVAL, "NULL argument");
   if (kmax < 3 || kmax > CS_KMAX_MAX) return fail(CS_EINVAL, "kmax must be in [3, %d], got %d", CS_KMAX_MAX, kmax);
-  if (path < CS_PATH_AUTO || path > CS_PATH_MFMA) return fail(CS_EINVAL, "bad path %d", path);
+  if (path < CS_PATH_AUTO || path > CS_PATH_MFMA_FP4) return fail(CS_EINVAL, "bad path %d", path);
+  if (path == CS_PATH_MFMA_FP4 && s->N >= (1 << 24))
+    return fail(CS_EINVAL, "the FP4 path needs N < 2^24 (exact fp32 sums)");
   if (!s->linked) return fail(CS_EINVAL, "set is not linked");
   return CS_OK;
 }
@@ -438,6 +462,8 @@ cs_status cs_interval_abundances(cs_ctx* ctx, cs_set* s, int kmax, uint64_t* out
   (void)hipSetDevice(ctx->device);
   std::vector<uint64_t> tot((size_t)kmax + 3, 0);
   if (path == CS_PATH_AUTO && (s->d == 2 || s->d == 4)) path = tuned_path(ctx, s->d, s->N);
+  if (path == CS_PATH_AUTO) path = choose_path(s->N, kmax);
+  s->last_path = path;
   if (s->N > 1) {
     rc = count_matrix(ctx, s->bits, s->N, s->W, kmax, path, tot.data(), nullptr, ctx->stream);
     if (rc != CS_OK) return rc;
@@ -484,6 +510,18 @@ cs_status cs_bd_action(cs_ctx* ctx, cs_set* s, double* S_out) {
   return CS_OK;
 }
 
+cs_status cs_smeared_action(cs_ctx* ctx, cs_set* s, double eps, double* S_out) {
+  if (!ctx || !s || !S_out) return fail(CS_EINVAL, "cs_smeared_action: NULL argument");
+  if (s->d != 2) return fail(CS_EINVAL, "cs_smeared_action: Eq. 5 is the 2D smeared action (set d=%d)", s->d);
+  if (!(eps > 0.0 && eps <= 1.0)) return fail(CS_EINVAL, "cs_smeared_action: eps must be in (0, 1]");
+  const int kmax = (int)std::max<int64_t>(s->N - 2, 3);
+  std::vector<uint64_t> hist((size_t)kmax + 1);
+  cs_status rc = cs_interval_abundances(ctx, s, kmax, hist.data(), nullptr, nullptr, CS_PATH_AUTO);
+  if (rc != CS_OK) return rc;
+  *S_out = smeared_action(s->N, hist.data(), (int64_t)hist.size(), eps);
+  return CS_OK;
+}
+
 cs_status cs_link_dev(int d, int64_t N, const double* coords_dev, uint64_t* bits_dev, int64_t stride_words,
                       void* hip_stream) {
   if (d != 2 && d != 4) return fail(CS_EINVAL, "cs_link_dev: d must be 2 or 4");
@@ -506,7 +544,9 @@ cs_status cs_count_dev(const uint64_t* bits_dev, int64_t N, int64_t stride_words
                        void* work_dev, int path, void* hip_stream) {
   if (N < 0) return fail(CS_EINVAL, "cs_count_dev: N < 0");
   if (kmax < 3 || kmax > CS_KMAX_MAX) return fail(CS_EINVAL, "cs_count_dev: bad kmax %d", kmax);
-  if (path < CS_PATH_AUTO || path > CS_PATH_MFMA) return fail(CS_EINVAL, "cs_count_dev: bad path");
+  if (path < CS_PATH_AUTO || path > CS_PATH_MFMA_FP4) return fail(CS_EINVAL, "cs_count_dev: bad path");
+  if (path == CS_PATH_MFMA_FP4 && N >= (1 << 24))
+    return fail(CS_EINVAL, "cs_count_dev: the FP4 path needs N < 2^24");
   if (!stats_dev || !work_dev || (N > 0 && !bits_dev)) return fail(CS_EINVAL, "cs_count_dev: NULL pointer");
   if (N > 0 && (stride_words < row_words(N) || stride_words % 4))
     return fail(CS_EINVAL, "cs_count_dev: stride must be >= %lld and a multiple of 4", (long long)row_words(N));

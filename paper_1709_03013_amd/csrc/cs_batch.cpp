@@ -24,9 +24,11 @@
 namespace cs {
 
 // ------------------------------------------------------------------ tuner
-// Picks the counting path per (d, ceil(log2 N)) by timing both kernels once
-// on a sprinkled set of that size; sizes above 32768 always use the MFMA
-// contraction (it wins asymptotically, and timing there costs seconds).
+// Picks the counting path per (d, ceil(log2 N)) by timing the three count
+// kernels once on a sprinkled set of that size (up to 32768 elements; larger
+// sets reuse the 32768 choice between the two matrix-core paths, since timing
+// there costs seconds).  The batch path runs sets tuned to either MFMA path
+// on its int8 persistent kernel.
 struct Tuner {
   std::mutex mu;
   std::map<std::pair<int, int>, int> best;
@@ -61,14 +63,17 @@ static double time_count(cs_ctx* ctx, const uint64_t* bits, int64_t N, int64_t W
 }
 
 int tuned_path(cs_ctx* ctx, int d, int64_t N) {
-  if (N > 32768) return CS_PATH_MFMA;
   if (N < 64) return CS_PATH_POP;
   if (!ctx->tuner) return choose_path(N, 3);
-  const int bucket = log2_bucket(N);
+  // beyond 32768 elements the choice measured at 32768 between the two
+  // matrix-core contractions carries over (both scale as N^3 there)
+  const bool large = N > 32768;
+  const int bucket = large ? 15 : log2_bucket(N);
   {
     std::lock_guard<std::mutex> g(ctx->tuner->mu);
     auto it = ctx->tuner->best.find({d, bucket});
-    if (it != ctx->tuner->best.end()) return it->second;
+    if (it != ctx->tuner->best.end())
+      return large && it->second == CS_PATH_POP ? CS_PATH_MFMA : it->second;
   }
   const int64_t Nt = (int64_t)1 << bucket;
   int path = choose_path(Nt, 3);
@@ -76,16 +81,21 @@ int tuned_path(cs_ctx* ctx, int d, int64_t N) {
   if (cs_sprinkle(ctx, d, Nt, 0x7475ull, &s) == CS_OK && cs_link(ctx, s) == CS_OK) {
     DevBuf ws(ctx->pool, (size_t)num_row_blocks(Nt) * 6 * 8);
     if (ws.p) {
-      const double tp = time_count(ctx, s->bits, Nt, s->W, CS_PATH_POP, (uint64_t*)ws.p);
-      const double tm = time_count(ctx, s->bits, Nt, s->W, CS_PATH_MFMA, (uint64_t*)ws.p);
-      path = tm < tp ? CS_PATH_MFMA : CS_PATH_POP;
+      double best = 1e300;
+      for (int p : {CS_PATH_POP, CS_PATH_MFMA, CS_PATH_MFMA_FP4}) {
+        const double t = time_count(ctx, s->bits, Nt, s->W, p, (uint64_t*)ws.p);
+        if (t < best) {
+          best = t;
+          path = p;
+        }
+      }
     }
   }
   if (s) cs_set_free(s);
   (void)hipGetLastError();
   std::lock_guard<std::mutex> g(ctx->tuner->mu);
   ctx->tuner->best[{d, bucket}] = path;
-  return path;
+  return large && path == CS_PATH_POP ? CS_PATH_MFMA : path;
 }
 
 void destroy_tuner(Tuner* t) { delete t; }
@@ -164,7 +174,7 @@ static cs_status build_plan(cs_ctx* ctx, BatchPlan* p) {
     for (int64_t ti = 0; ti < (N + 63) / 64; ++ti)
       for (int64_t tw = 0; tw < (bs.W + 63) / 64; ++tw) link_items.push_back(pack_item(s, ti, tw));
     if (N < 2) continue;
-    if (bs.path == CS_PATH_MFMA) {
+    if (bs.path == CS_PATH_MFMA || bs.path == CS_PATH_MFMA_FP4) {
       const int64_t nb = (N + 255) / 256;
       for (int64_t a = 0; a < nb; ++a)
         for (int64_t b = a; b < nb; ++b) mfma.push_back({16 * (b - a + 1) + 4, pack_item(s, a, b)});

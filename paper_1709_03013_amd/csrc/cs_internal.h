@@ -23,6 +23,9 @@ struct SortRec {
 };
 
 constexpr int kSortTile = 2048;  // records sorted per workgroup in LDS
+// Full-histogram counting keeps bins 0..kLdsBins-1 in LDS per workgroup and
+// adds larger interval sizes straight to the row-block stats in HBM.
+constexpr int kLdsBins = 8192;
 constexpr int kRowBlock = CS_ROW_BLOCK;
 
 inline int64_t row_words(int64_t N) {
@@ -58,6 +61,8 @@ hipError_t launch_count_pop(const uint64_t* bits, int64_t N, int64_t W,
                             int kmax, uint64_t* rb_stats, hipStream_t st);
 hipError_t launch_count_mfma(const uint64_t* bits, int64_t N, int64_t W,
                              int kmax, uint64_t* rb_stats, hipStream_t st);
+hipError_t launch_count_mfma_fp4(const uint64_t* bits, int64_t N, int64_t W,
+                                 int kmax, uint64_t* rb_stats, hipStream_t st);
 // Sum the row-block stats into tot (kmax+3 words).
 hipError_t launch_reduce_rows(const uint64_t* rb_stats, int64_t nrb,
                               int kmax, uint64_t* tot, hipStream_t st);

@@ -68,6 +68,7 @@ struct cs_set {
   uint64_t* bits = nullptr;  // N*W words
   bool linked = false;
   int counted_kmax = -1;
+  int last_path = 0;  // count path used by the last cs_interval_abundances
   uint64_t n[4] = {0, 0, 0, 0};
   uint64_t R = 0, summ = 0;
 };

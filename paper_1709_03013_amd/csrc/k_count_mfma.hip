@@ -23,6 +23,7 @@
 // with i < j and bit (i, j) set, bins m, and adds R and the sum of m, with
 // one atomic per counter per wave into the tile's row-block stats.
 #include <cstdlib>
+#include <type_traits>
 
 #include "cs_device.h"
 #include "cs_internal.h"
@@ -31,7 +32,9 @@ namespace cs {
 namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
 typedef int v16i __attribute__((ext_vector_type(16)));
+typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int kBT = 256;  // pairs per block-tile side (= row block)
 
@@ -63,11 +66,33 @@ __device__ __forceinline__ v4i spread4(uint32_t D, int r0) {
   return f;
 }
 
+// The 32 bits of D as one FP4 (e2m1) MFMA operand: nibble p of dword r is
+// 1.0 (0b0010) when bit 4p + r of D is set, else 0.  Products of 0/1 values
+// summed in fp32 are exact integers up to 2^24 > N.  Only the first four
+// dwords of the 8-dword operand are read for FP4.
+__device__ __forceinline__ v8i spread_fp4(uint32_t D) {
+  const uint32_t M = 0x22222222u;
+  v8i f;
+  f[0] = (int)((D << 1) & M);
+  f[1] = (int)(D & M);
+  f[2] = (int)((D >> 1) & M);
+  f[3] = (int)((D >> 2) & M);
+  f[4] = 0;
+  f[5] = 0;
+  f[6] = 0;
+  f[7] = 0;
+  return f;
+}
+
 // WM x WN waves over the 256x256 tile; each wave owns (256/WM) x (256/WN)
-// pairs as TM x TN tiles of 32x32.
+// pairs as TM x TN tiles of 32x32.  FP4 selects the e2m1 contraction
+// (v_mfma_scale_f32_32x32x64_f8f6f4, unit scales) instead of int8: one MFMA
+// per 32 bits of each operand row instead of two.
 // One 256x256 tile of pairs (row block BI <= column block BJ) by one
-// workgroup.  lds_hist (FULL only) holds kmax+2 zeroed bins.
-template <int WM, int WN, bool FULL>
+// workgroup.  lds_hist (FULL only) holds lb+1 zeroed bins, lb =
+// min(kmax+1, kLdsBins) (the last one a spare); larger sizes go straight to
+// the row-block stats.
+template <int WM, int WN, bool FULL, bool FP4 = false>
 __device__ __forceinline__ void mfma_tile(const uint64_t* __restrict__ bits, int64_t N,
                                           int64_t W, int64_t BI, int64_t BJ, int kmax,
                                           uint64_t* __restrict__ rb_stats,
@@ -101,7 +126,8 @@ __device__ __forceinline__ void mfma_tile(const uint64_t* __restrict__ bits, int
     boffs[t] = BJ * kBT + rel < N ? (uint32_t)(rel * W * 8) : 0u;
   }
 
-  v16i acc[TM][TN];
+  using Acc = typename std::conditional<FP4, v16f, v16i>::type;
+  Acc acc[TM][TN];
 #pragma unroll
   for (int a = 0; a < TM; ++a)
 #pragma unroll
@@ -147,21 +173,38 @@ __device__ __forceinline__ void mfma_tile(const uint64_t* __restrict__ bits, int
         for (int q = 0; q < 4; ++q)
           xb[t][q] &= (uint32_t)(mask_below(J0 + 32 * t + r32, 4 * c + 2 * g + (q >> 1)) >> (32 * (q & 1)));
     }
+    if constexpr (FP4) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+      for (int q = 0; q < 4; ++q) {
+        v8i fa[TM], fb[TN];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        v4i fa[TM], fb[TN];
+        for (int t = 0; t < TM; ++t) fa[t] = spread_fp4(xa[t][q]);
 #pragma unroll
-        for (int t = 0; t < TM; ++t) fa[t] = spread4(xa[t][q], 4 * h);
-#pragma unroll
-        for (int t = 0; t < TN; ++t) fb[t] = spread4(xb[t][q], 4 * h);
+        for (int t = 0; t < TN; ++t) fb[t] = spread_fp4(xb[t][q]);
 #pragma unroll
         for (int a = 0; a < TM; ++a)
 #pragma unroll
           for (int b = 0; b < TN; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                fa[a], fb[b], acc[a][b], 4, 4, 0, 127, 0, 127);
       }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          v4i fa[TM], fb[TN];
+#pragma unroll
+          for (int t = 0; t < TM; ++t) fa[t] = spread4(xa[t][q], 4 * h);
+#pragma unroll
+          for (int t = 0; t < TN; ++t) fb[t] = spread4(xb[t][q], 4 * h);
+#pragma unroll
+          for (int a = 0; a < TM; ++a)
+#pragma unroll
+            for (int b = 0; b < TN; ++b)
+              acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
+        }
+    }
   };
   load_chunk(c0);
   if (c0 == c1) {
@@ -181,6 +224,8 @@ __device__ __forceinline__ void mfma_tile(const uint64_t* __restrict__ bits, int
   uint32_t cnt[4] = {0, 0, 0, 0};
   uint32_t nrel = 0;
   uint64_t summ = 0;
+  uint64_t* st = rb_stats + BI * (int64_t)(kmax + 3);
+  const uint32_t lb = (uint32_t)(kmax + 1 < kLdsBins ? kmax + 1 : kLdsBins);
 #pragma unroll
   for (int b = 0; b < TN; ++b) {
     const int64_t j = J0 + 32 * b + r32;
@@ -201,8 +246,9 @@ __device__ __forceinline__ void mfma_tile(const uint64_t* __restrict__ bits, int
         nrel += valid ? 1u : 0u;
         summ += valid ? m : 0u;
         if constexpr (FULL) {
-          const bool hit = valid && m <= (uint32_t)kmax;
-          atomicAdd(&lds_hist[hit ? m : (uint32_t)kmax + 1], 1u);
+          atomicAdd(&lds_hist[valid && m < lb ? m : lb], 1u);
+          if (valid && m >= lb && m <= (uint32_t)kmax)
+            atomicAdd((unsigned long long*)&st[m], 1ull);
         } else {
 #pragma unroll
           for (int k = 0; k < 4; ++k) cnt[k] += (valid && m == (uint32_t)k) ? 1u : 0u;
@@ -212,7 +258,6 @@ __device__ __forceinline__ void mfma_tile(const uint64_t* __restrict__ bits, int
   }
   nrel = wave_sum_u32(nrel);
   summ = wave_sum_u64(summ);
-  uint64_t* st = rb_stats + BI * (int64_t)(kmax + 3);
   if constexpr (!FULL) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) cnt[k] = wave_sum_u32(cnt[k]);
@@ -222,7 +267,7 @@ __device__ __forceinline__ void mfma_tile(const uint64_t* __restrict__ bits, int
     }
   } else {
     __syncthreads();
-    for (int b = tid; b <= kmax; b += kThreads) {
+    for (int b = tid; b < (int)lb; b += kThreads) {
       const uint32_t v = lds_hist[b];
       if (v) atomicAdd((unsigned long long*)&st[b], (unsigned long long)v);
     }
@@ -233,18 +278,19 @@ __device__ __forceinline__ void mfma_tile(const uint64_t* __restrict__ bits, int
   }
 }
 
-template <int WM, int WN, bool FULL>
+template <int WM, int WN, bool FULL, bool FP4>
 __global__ __launch_bounds__(64 * WM * WN, 1) void k_count_mfma(
     const uint64_t* __restrict__ bits, int64_t N, int64_t W, int64_t nb,
     int kmax, uint64_t* __restrict__ rb_stats) {
-  extern __shared__ uint32_t lds_hist[];  // FULL only: kmax+2 bins
+  extern __shared__ uint32_t lds_hist[];  // FULL only: lb+1 bins
   int64_t BI, BJ;
   tri_tile_longest_first((int64_t)blockIdx.x, nb, &BI, &BJ);
   if constexpr (FULL) {
-    for (int b = threadIdx.x; b <= kmax + 1; b += 64 * WM * WN) lds_hist[b] = 0;
+    const int lb = kmax + 1 < kLdsBins ? kmax + 1 : kLdsBins;
+    for (int b = threadIdx.x; b <= lb; b += 64 * WM * WN) lds_hist[b] = 0;
     __syncthreads();
   }
-  mfma_tile<WM, WN, FULL>(bits, N, W, BI, BJ, kmax, rb_stats, lds_hist);
+  mfma_tile<WM, WN, FULL, FP4>(bits, N, W, BI, BJ, kmax, rb_stats, lds_hist);
 }
 
 // Batched, persistent: each workgroup takes (set, BI, BJ) items from a device
@@ -266,7 +312,7 @@ __global__ __launch_bounds__(512, 1) void k_batch_count_mfma(BatchDev b) {
   }
 }
 
-template <int WM, int WN>
+template <int WM, int WN, bool FP4>
 hipError_t launch_variant(const uint64_t* bits, int64_t N, int64_t W, int kmax,
                           uint64_t* rb_stats, hipStream_t st) {
   const int64_t nb = (N + kBT - 1) / kBT;
@@ -274,11 +320,11 @@ hipError_t launch_variant(const uint64_t* bits, int64_t N, int64_t W, int kmax,
   if (ntiles > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 block(64 * WM * WN);
   if (kmax <= 3) {
-    hipLaunchKernelGGL((k_count_mfma<WM, WN, false>), dim3((unsigned)ntiles), block, 0, st,
+    hipLaunchKernelGGL((k_count_mfma<WM, WN, false, FP4>), dim3((unsigned)ntiles), block, 0, st,
                        bits, N, W, nb, kmax, rb_stats);
   } else {
-    const size_t lds = (size_t)(kmax + 2) * sizeof(uint32_t);
-    hipLaunchKernelGGL((k_count_mfma<WM, WN, true>), dim3((unsigned)ntiles), block, lds, st,
+    const size_t lds = (size_t)((kmax + 1 < kLdsBins ? kmax + 1 : kLdsBins) + 1) * sizeof(uint32_t);
+    hipLaunchKernelGGL((k_count_mfma<WM, WN, true, FP4>), dim3((unsigned)ntiles), block, lds, st,
                        bits, N, W, nb, kmax, rb_stats);
   }
   return hipGetLastError();
@@ -300,8 +346,14 @@ hipError_t launch_count_mfma(const uint64_t* bits, int64_t N, int64_t W, int kma
                              uint64_t* rb_stats, hipStream_t st) {
   static_assert(kBT == kRowBlock, "block tile must equal the stats row block");
   if (N <= 1) return hipSuccess;
-  if (mfma_variant() == 1) return launch_variant<2, 4>(bits, N, W, kmax, rb_stats, st);
-  return launch_variant<2, 2>(bits, N, W, kmax, rb_stats, st);
+  if (mfma_variant() == 1) return launch_variant<2, 4, false>(bits, N, W, kmax, rb_stats, st);
+  return launch_variant<2, 2, false>(bits, N, W, kmax, rb_stats, st);
+}
+
+hipError_t launch_count_mfma_fp4(const uint64_t* bits, int64_t N, int64_t W, int kmax,
+                                 uint64_t* rb_stats, hipStream_t st) {
+  if (N <= 1) return hipSuccess;
+  return launch_variant<2, 4, true>(bits, N, W, kmax, rb_stats, st);
 }
 
 hipError_t launch_batch_count_mfma(const BatchDev& b, int grid, hipStream_t st) {

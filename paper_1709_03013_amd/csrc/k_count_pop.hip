@@ -29,7 +29,8 @@ constexpr int kChunk = 4;  // words per staging step (rows are 4-word aligned)
 
 // One 64x64 tile of pairs (rows of block bi against rows of block bj >= bi)
 // by one 64-lane workgroup.  sI, sJ: word-major staging, sI[k][r] = word
-// (w+k) of row 64bi+r.  lds_hist (FULL only) holds kmax+1 zeroed bins.
+// (w+k) of row 64bi+r.  lds_hist (FULL only) holds min(kmax+1, kLdsBins)
+// zeroed bins; larger sizes go straight to the row-block stats.
 template <bool FULL>
 __device__ __forceinline__ void pop_tile(const uint64_t* __restrict__ bits, int64_t N,
                                          int64_t W, int64_t bi, int64_t bj, int kmax,
@@ -103,6 +104,8 @@ __device__ __forceinline__ void pop_tile(const uint64_t* __restrict__ bits, int6
   uint32_t cnt[4] = {0, 0, 0, 0};
   uint32_t nrel = 0;
   uint64_t summ = 0;
+  uint64_t* st = rb_stats + ((bi * 64) / kRowBlock) * (int64_t)(kmax + 3);
+  const uint32_t lb = (uint32_t)(kmax + 1 < kLdsBins ? kmax + 1 : kLdsBins);
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
     const int64_t i = bi * 64 + 8 * li + a;
@@ -115,7 +118,10 @@ __device__ __forceinline__ void pop_tile(const uint64_t* __restrict__ bits, int6
       nrel += valid ? 1u : 0u;
       summ += valid ? m : 0u;
       if constexpr (FULL) {
-        if (valid && m <= (uint32_t)kmax) atomicAdd(&lds_hist[m], 1u);
+        if (valid && m <= (uint32_t)kmax) {
+          if (m < lb) atomicAdd(&lds_hist[m], 1u);
+          else atomicAdd((unsigned long long*)&st[m], 1ull);
+        }
       } else {
 #pragma unroll
         for (int k = 0; k < 4; ++k) cnt[k] += (valid && m == (uint32_t)k) ? 1u : 0u;
@@ -124,7 +130,6 @@ __device__ __forceinline__ void pop_tile(const uint64_t* __restrict__ bits, int6
   }
   nrel = wave_sum_u32(nrel);
   summ = wave_sum_u64(summ);
-  uint64_t* st = rb_stats + ((bi * 64) / kRowBlock) * (int64_t)(kmax + 3);
   if constexpr (!FULL) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) cnt[k] = wave_sum_u32(cnt[k]);
@@ -134,7 +139,7 @@ __device__ __forceinline__ void pop_tile(const uint64_t* __restrict__ bits, int6
     }
   } else {
     __syncthreads();
-    for (int b = lane; b <= kmax; b += 64) {
+    for (int b = lane; b < (int)lb; b += 64) {
       const uint32_t v = lds_hist[b];
       if (v) atomicAdd((unsigned long long*)&st[b], (unsigned long long)v);
     }
@@ -151,11 +156,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
     int kmax, uint64_t* __restrict__ rb_stats) {
   __shared__ uint64_t sI[kChunk][64];
   __shared__ uint64_t sJ[kChunk][64];
-  extern __shared__ uint32_t lds_hist[];  // FULL only: kmax+1 bins
+  extern __shared__ uint32_t lds_hist[];  // FULL only: min(kmax+1, kLdsBins) bins
   int64_t bi, bj;
   tri_tile_longest_first((int64_t)blockIdx.x, nb, &bi, &bj);
   if constexpr (FULL) {
-    for (int b = threadIdx.x; b <= kmax; b += 64) lds_hist[b] = 0;
+    const int lb = kmax + 1 < kLdsBins ? kmax + 1 : kLdsBins;
+    for (int b = threadIdx.x; b < lb; b += 64) lds_hist[b] = 0;
   }
   pop_tile<FULL>(bits, N, W, bi, bj, kmax, rb_stats, lds_hist, sI, sJ);
 }
@@ -245,7 +251,7 @@ hipError_t launch_count_pop(const uint64_t* bits, int64_t N, int64_t W,
     hipLaunchKernelGGL(k_count_pop<false>, dim3((unsigned)ntiles), dim3(64), 0, st,
                        bits, N, W, nb, kmax, rb_stats);
   } else {
-    const size_t lds = (size_t)(kmax + 1) * sizeof(uint32_t);
+    const size_t lds = (size_t)(kmax + 1 < kLdsBins ? kmax + 1 : kLdsBins) * sizeof(uint32_t);
     hipLaunchKernelGGL(k_count_pop<true>, dim3((unsigned)ntiles), dim3(64), lds, st,
                        bits, N, W, nb, kmax, rb_stats);
   }

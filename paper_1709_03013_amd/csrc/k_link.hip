@@ -2,9 +2,9 @@
 // zero-diagonal causal matrix from time-sorted coordinates.
 //
 // gfx950 design: a wave's 64 lanes are 64 consecutive columns k of one
-// 64-bit word; for each row i (wave-uniform, coordinates in scalar
-// registers) the 64 relation tests produce the word directly as the
-// wave's compare mask (ballot).  Word (i, w) is kept by lane i%64, so after
+// 64-bit word; for each row i (wave-uniform, coordinates broadcast from LDS)
+// the 64 relation tests produce the word directly as the wave's compare mask
+// (ballot).  Word (i, w) is kept by lane i%64, so after
 // 64 rows every lane holds one word of a 64x64-word tile, which is staged in
 // LDS and stored row by row with fully coalesced 512-byte rows.
 //
@@ -27,11 +27,17 @@ struct Pt {
   double c[D];
 };
 
-template <int D>
-__device__ __forceinline__ bool related_sym(const Pt<D>& a, const Pt<D>& b) {
+// Relation of two elements (Sec. 1.1, strict).  DIR: 0 = either order (the
+// diagonal 64x64 block), 1 = a before b (columns after the rows), 2 = b
+// before a.  Bitwise & and | keep the test free of branches.
+template <int D, int DIR>
+__device__ __forceinline__ bool related_dir(const Pt<D>& a, const Pt<D>& b) {
   if constexpr (D == 2) {
-    return (a.c[0] < b.c[0] && a.c[1] < b.c[1]) ||
-           (b.c[0] < a.c[0] && b.c[1] < a.c[1]);
+    const bool fwd = (a.c[0] < b.c[0]) & (a.c[1] < b.c[1]);
+    const bool bwd = (b.c[0] < a.c[0]) & (b.c[1] < a.c[1]);
+    if constexpr (DIR == 1) return fwd;
+    if constexpr (DIR == 2) return bwd;
+    return fwd | bwd;
   } else {
     const double dt = b.c[0] - a.c[0];
     const double dx = b.c[1] - a.c[1];
@@ -43,16 +49,43 @@ __device__ __forceinline__ bool related_sym(const Pt<D>& a, const Pt<D>& b) {
   }
 }
 
+// 64 relation words of one column word: lane r ends with word (i0 + r, w).
+template <int D, int DIR>
+__device__ __forceinline__ uint64_t link_word(const double (*rowc)[64], const Pt<D>& pk,
+                                              bool kval) {
+  const int lane = threadIdx.x & 63;
+  uint64_t my = 0;
+#pragma unroll 16
+  for (int r = 0; r < 64; ++r) {
+    Pt<D> pi;
+#pragma unroll
+    for (int q = 0; q < D; ++q) pi.c[q] = rowc[q][r];
+    const bool rel = kval & related_dir<D, DIR>(pi, pk);
+    const uint64_t m = __ballot(rel);
+    my = lane == r ? m : my;
+  }
+  return my;
+}
+
 // One 64-row x 64-word tile of the matrix, rows i0.., words w0.. (256 threads).
+// The 64 rows' coordinates are staged in LDS and read as broadcasts; each
+// wave builds 16 words, one column word (64 columns, one per lane) at a time,
+// and the tile leaves through LDS as coalesced 512-byte row segments.  Off
+// the diagonal block only one order of each pair can hold (labels are
+// time-sorted), so only that direction is tested.
 template <int D>
 __device__ __forceinline__ void link_tile(const double* __restrict__ coords, int64_t N,
                                           uint64_t* __restrict__ bits, int64_t W,
                                           int64_t i0, int64_t w0,
-                                          uint64_t (*tile)[65]) {
+                                          uint64_t (*tile)[65], double (*rowc)[64]) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int64_t rem = N - i0;
-  const int nrows = rem < 64 ? (int)rem : 64;
+  if (threadIdx.x < 64) {
+    const int64_t i = i0 + lane;
+#pragma unroll
+    for (int q = 0; q < D; ++q) rowc[q][lane] = i < N ? coords[(int64_t)q * N + i] : 0.0;
+  }
+  __syncthreads();
   for (int wl = 0; wl < 16; ++wl) {
     const int wloc = wave * 16 + wl;
     const int64_t w = w0 + wloc;
@@ -64,15 +97,12 @@ __device__ __forceinline__ void link_tile(const double* __restrict__ coords, int
       Pt<D> pk;
 #pragma unroll
       for (int q = 0; q < D; ++q) pk.c[q] = coords[(int64_t)q * N + kk];
-      for (int r = 0; r < nrows; ++r) {
-        const int64_t i = i0 + r;
-        Pt<D> pi;
-#pragma unroll
-        for (int q = 0; q < D; ++q) pi.c[q] = coords[(int64_t)q * N + i];
-        const bool rel = kval && related_sym<D>(pi, pk);
-        const uint64_t m = __ballot(rel);
-        my = lane == r ? m : my;
-      }
+      if (w * 64 >= i0 + 64)
+        my = link_word<D, 1>(rowc, pk, kval);
+      else if (w * 64 + 64 <= i0)
+        my = link_word<D, 2>(rowc, pk, kval);
+      else
+        my = link_word<D, 0>(rowc, pk, kval);
     }
     tile[lane][wloc] = my;
   }
@@ -91,19 +121,23 @@ __global__ __launch_bounds__(256) void k_link(const double* __restrict__ coords,
                                               uint64_t* __restrict__ bits,
                                               int64_t W) {
   __shared__ uint64_t tile[64][65];
-  link_tile<D>(coords, N, bits, W, (int64_t)blockIdx.y * 64, (int64_t)blockIdx.x * 64, tile);
+  __shared__ double rowc[D][64];
+  link_tile<D>(coords, N, bits, W, (int64_t)blockIdx.y * 64, (int64_t)blockIdx.x * 64, tile, rowc);
 }
 
 // Batched: one workgroup per (set, 64-row tile, 64-word tile) item.
 __global__ __launch_bounds__(256) void k_batch_link(BatchDev b) {
   __shared__ uint64_t tile[64][65];
+  __shared__ double rowc[4][64];
   int64_t set, ti, tw;
   unpack_item(b.link_items[blockIdx.x], &set, &ti, &tw);
   const BatchSet bs = b.sets[set];
   if (bs.d == 2)
-    link_tile<2>(b.coords + bs.coords_off, bs.N, b.bits + bs.bits_off, bs.W, ti * 64, tw * 64, tile);
+    link_tile<2>(b.coords + bs.coords_off, bs.N, b.bits + bs.bits_off, bs.W, ti * 64, tw * 64, tile,
+                 rowc);
   else
-    link_tile<4>(b.coords + bs.coords_off, bs.N, b.bits + bs.bits_off, bs.W, ti * 64, tw * 64, tile);
+    link_tile<4>(b.coords + bs.coords_off, bs.N, b.bits + bs.bits_off, bs.W, ti * 64, tw * 64, tile,
+                 rowc);
 }
 
 __global__ __launch_bounds__(256) void k_fill_u64(uint64_t* __restrict__ p,

@@ -71,7 +71,7 @@ def test_sprinkle_and_link_match_oracle(cs, ctx, d, N, seed):
 
 
 # ------------------------------------------------------------------- counts
-@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("path", [1, 2, 3])
 @pytest.mark.parametrize("d,N,seed", [(2, 2, 1), (2, 3, 2), (2, 64, 3), (2, 65, 4), (2, 200, 5),
                                       (2, 1024, 1), (2, 1500, 12), (4, 64, 6), (4, 300, 7),
                                       (4, 2048, 14), (4, 2500, 15)])
@@ -90,7 +90,7 @@ def test_counts_match_oracle(cs, ctx, d, N, seed, path):
         cs.cs_set_free(s)
 
 
-@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("path", [1, 2, 3])
 @pytest.mark.parametrize("kmax", [4, 17, 200])
 @pytest.mark.parametrize("d,N,seed", [(2, 700, 31), (4, 1100, 32)])
 def test_full_histogram_matches_oracle(cs, ctx, d, N, seed, kmax, path):
@@ -105,7 +105,7 @@ def test_full_histogram_matches_oracle(cs, ctx, d, N, seed, kmax, path):
         cs.cs_set_free(s)
 
 
-@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("path", [1, 2, 3])
 def test_row_block_stats_match_oracle(cs, ctx, path):
     d, N, seed = 2, 1300, 41
     say("case rowblocks N=%d path=%d" % (N, path))
@@ -136,7 +136,7 @@ def injected_cases():
     ]
 
 
-@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("path", [1, 2, 3])
 @pytest.mark.parametrize("name,order", injected_cases(), ids=[c[0] for c in injected_cases()])
 def test_injected_orders(cs, ctx, name, order, path):
     say("case injected %s path=%d" % (name, path))
@@ -251,7 +251,7 @@ def golden(name):
     return g[name]
 
 
-@pytest.mark.parametrize("path", [0, 1, 2])
+@pytest.mark.parametrize("path", [0, 1, 2, 3])
 @pytest.mark.parametrize("name", ["2d_1024", "4d_16384"])
 def test_workload_matches_stored_oracle(cs, ctx, name, path):
     g = golden(name)
@@ -282,7 +282,7 @@ def test_full_size_2d_131072_against_stored_oracle(cs, ctx):
     try:
         bits = cs.cs_get_bitset(ctx, s)
         assert hashlib.sha256(bits.tobytes()).hexdigest() == g["bitset_sha256"]
-        for path in (0, 2, 1):
+        for path in (0, 3, 2, 1):
             say("  path %d" % path)
             n, R, sm = cs.cs_interval_abundances(ctx, s, 3, path)
             assert [int(x) for x in n] == g["n"] and R == g["R"] and sm == g["summ"]
@@ -296,3 +296,48 @@ def test_full_size_2d_131072_against_stored_oracle(cs, ctx):
             assert list(blocks[b, :4]) == list(h) and blocks[b, 4] == R and blocks[b, 5] == sm
     finally:
         cs.cs_set_free(s)
+
+
+@pytest.mark.parametrize("path", [1, 2, 3])
+@pytest.mark.parametrize("d,N,seed", [(2, 9000, 61), (4, 9500, 62)])
+def test_full_histogram_beyond_lds_bins(cs, ctx, d, N, seed, path):
+    """kmax = N-2 > 8191: small sizes are binned in LDS, larger ones with
+    device atomics; the whole histogram equals the oracle's."""
+    say("case fullhist N-2 d=%d N=%d path=%d" % (d, N, path))
+    s = gpu_set(cs, ctx, d, N, seed)
+    try:
+        n, R, sm = cs.cs_interval_abundances(ctx, s, N - 2, path)
+        oc, _, _ = oracle.sprinkle(d, N, seed)
+        h, oR, osm = oracle.count_bits(oracle.link(d, oc), N, nbins=N - 1)
+        assert np.array_equal(n, h) and R == oR and sm == osm
+    finally:
+        cs.cs_set_free(s)
+
+
+@pytest.mark.parametrize("eps", [1.0, 0.5, 2.0**-6])
+@pytest.mark.parametrize("N,seed", [(300, 71), (2048, 72), (5000, 73)])
+def test_smeared_action_matches_oracle(cs, ctx, N, seed, eps):
+    say("case smeared N=%d eps=%r" % (N, eps))
+    s = gpu_set(cs, ctx, 2, N, seed)
+    try:
+        S = cs.cs_smeared_action(ctx, s, eps)
+        oc, _, _ = oracle.sprinkle(2, N, seed)
+        h, _, _ = oracle.count_bits(oracle.link(2, oc), N, nbins=N - 1)
+        So = oracle.smeared_action(N, h, eps)
+        assert S == So, (S, So)
+        if eps == 1.0:
+            assert S == cs.cs_bd_action(ctx, s)
+    finally:
+        cs.cs_set_free(s)
+
+
+def test_smeared_action_rejects_bad_arguments(cs, ctx):
+    s = gpu_set(cs, ctx, 4, 100, 1)
+    with pytest.raises(cs.CsError):
+        cs.cs_smeared_action(ctx, s, 0.5)          # 4D
+    cs.cs_set_free(s)
+    s = gpu_set(cs, ctx, 2, 100, 1)
+    for bad in (0.0, -0.1, 1.5):
+        with pytest.raises(cs.CsError):
+            cs.cs_smeared_action(ctx, s, bad)
+    cs.cs_set_free(s)
