@@ -12,7 +12,9 @@ Two tiers, both written from the paper's definitions (arXiv:1709.03013):
   timelike relation (Sec. 1.1), the packed symmetric matrix (Sec. 2.2,
   Sec. 3.2), the triple-loop interval count of Sec. 4.1 (tier 1), the masked
   AND + popcount count of Fig. 2 / Alg. 5 over the bitset (tier 2), the
-  3-chain identity and the BD action (Eq. 4; 4D weights are a reading).
+  3-chain identity and the BD action (Eq. 4; 4D weights are a reading), the
+  smeared action (Eq. 5), and the (1+1) de Sitter slab of Sec. 6.1 (Eq. 9):
+  sprinkle uniform in w = tan(eta) and in angle, and its relation.
 * ``brute.py``: pure-Python brute force for tiny sets, used to pin the C code.
 
 Every function here has pins in ``tests/test_oracle_*.py``; the 4D action
@@ -83,6 +85,12 @@ def lib() -> ctypes.CDLL:
         L.orc_bd_action.restype = ctypes.c_double
         L.orc_smeared_action.argtypes = [ctypes.c_int64, _u64p, ctypes.c_int64, ctypes.c_double]
         L.orc_smeared_action.restype = ctypes.c_double
+        L.orc_sprinkle_desitter.argtypes = [ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, _dp, _i64p]
+        L.orc_sprinkle_desitter.restype = ctypes.c_int64
+        L.orc_related_desitter.argtypes = [_dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
+        L.orc_related_desitter.restype = ctypes.c_int
+        L.orc_link_desitter.argtypes = [_dp, ctypes.c_int64, _u64p, ctypes.c_int64]
+        L.orc_link_desitter.restype = None
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = ctypes.c_int
         _lib = L
@@ -185,6 +193,33 @@ def smeared_action(N: int, hist, eps: float) -> float:
     """Eq. 5 from the full histogram hist[k] = N_k (k = 0..len-1)."""
     h = np.ascontiguousarray(np.asarray(hist, dtype=np.uint64))
     return float(lib().orc_smeared_action(N, _p(h, _u64p), h.size, eps))
+
+
+def sprinkle_desitter(N: int, seed: int, eta0: float):
+    """(1+1) de Sitter slab: sorted (w = tan eta, x, y) SoA, generation index,
+    Philox blocks drawn.  w0 = tan(eta0) is rounded once by the host libm."""
+    import math
+    coords = np.zeros((3, max(N, 0)), dtype=np.float64)
+    orig = np.zeros(max(N, 0), dtype=np.int64)
+    drawn = lib().orc_sprinkle_desitter(N, seed & (2**64 - 1), math.tan(eta0), _p(coords, _dp), _p(orig, _i64p))
+    if drawn < 0:
+        raise ValueError("bad sprinkle arguments")
+    return coords, orig, int(drawn)
+
+
+def related_desitter(coords: np.ndarray, i: int, j: int) -> bool:
+    c = np.ascontiguousarray(coords, dtype=np.float64)
+    return bool(lib().orc_related_desitter(_p(c, _dp), c.shape[1], i, j))
+
+
+def link_desitter(coords: np.ndarray) -> np.ndarray:
+    c = np.ascontiguousarray(coords, dtype=np.float64)
+    N = c.shape[1]
+    W = row_words(N)
+    bits = np.zeros((N, W), dtype=np.uint64)
+    if N:
+        lib().orc_link_desitter(_p(c, _dp), N, _p(bits, _u64p), W)
+    return bits
 
 
 def num_threads() -> int:

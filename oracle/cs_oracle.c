@@ -303,6 +303,105 @@ void orc_count_bits(const uint64_t* bits, int64_t N, int64_t W, int64_t i_lo,
   *summ_out = summ;
 }
 
+/* ------------------------------------------------------------------------ */
+/* (1+1) de Sitter slab (Sec. 6.1, Eq. 9): ds^2 = sec^2(eta)(-deta^2 +       */
+/* dtheta^2), eta in [-eta0, eta0], theta in [0, 2 pi).  The volume element  */
+/* sec^2(eta) deta dtheta = dw dtheta with w = tan(eta), so elements are     */
+/* uniform in w in [-w0, w0], w0 = tan(eta0), and in theta.  theta is kept   */
+/* as an unnormalised direction (x, y) drawn uniformly from the unit disk:   */
+/* only differences of angles enter, and tan of a difference is cross/dot.   */
+/* Element c, attempt a = 0, 1, ..., 63: Philox at counter (c, a, 0, 0), key */
+/* (seed, 5): w = (2 dbl(r0) - 1) w0, x = 2 dbl(r1) - 1, y = 2 dbl(r2) - 1,  */
+/* accepted iff 0 < x*x + y*y < 1 (after 64 rejections (x, y) = (1, 0)).     */
+/* Labels sorted by w, then c.  coords: 3 arrays (w, x, y).                 */
+/* ------------------------------------------------------------------------ */
+#define TAG_DS 5ULL
+
+typedef struct {
+  double w;
+  int64_t idx;
+} orc_wkey;
+
+static int wkey_cmp(const void* pa, const void* pb) {
+  const orc_wkey* a = (const orc_wkey*)pa;
+  const orc_wkey* b = (const orc_wkey*)pb;
+  if (a->w != b->w) return a->w < b->w ? -1 : 1;
+  if (a->idx != b->idx) return a->idx < b->idx ? -1 : 1;
+  return 0;
+}
+
+int64_t orc_sprinkle_desitter(int64_t N, uint64_t seed, double w0, double* coords,
+                              int64_t* orig) {
+  if (N < 0) return -1;
+  if (N == 0) return 0;
+  const uint64_t key[2] = {seed, TAG_DS};
+  orc_wkey* keys = (orc_wkey*)malloc((size_t)N * sizeof(orc_wkey));
+  double* raw = (double*)malloc((size_t)N * 3 * sizeof(double));
+  int64_t draws = 0;
+  for (int64_t c = 0; c < N; ++c) {
+    double w = 0.0, x = 1.0, y = 0.0;
+    for (uint64_t a = 0; a < 64; ++a) {
+      uint64_t ctr[4] = {(uint64_t)c, a, 0, 0}, r[4];
+      orc_philox4x64_10(ctr, key, r);
+      ++draws;
+      const double wc = (2.0 * unit_double(r[0]) - 1.0) * w0;
+      const double xc = 2.0 * unit_double(r[1]) - 1.0;
+      const double yc = 2.0 * unit_double(r[2]) - 1.0;
+      const double rr = xc * xc + yc * yc;
+      w = wc;
+      if (rr > 0.0 && rr < 1.0) {
+        x = xc;
+        y = yc;
+        break;
+      }
+      x = 1.0;
+      y = 0.0;
+    }
+    raw[c] = w;
+    raw[N + c] = x;
+    raw[2 * N + c] = y;
+    keys[c].w = w;
+    keys[c].idx = c;
+  }
+  qsort(keys, (size_t)N, sizeof(orc_wkey), wkey_cmp);
+  for (int64_t s = 0; s < N; ++s) {
+    const int64_t g = keys[s].idx;
+    for (int q = 0; q < 3; ++q) coords[(int64_t)q * N + s] = raw[(int64_t)q * N + g];
+    if (orig) orig[s] = g;
+  }
+  free(keys);
+  free(raw);
+  return draws;
+}
+
+/* de Sitter relation (strict): |deta| > pi - |pi - |dtheta||.  For eta0 <
+ * pi/4 both sides are below pi/2 when dot > 0, and tan is increasing there:
+ * tan|deta| = |wi - wj| / (1 + wi wj), tan(dtheta) = |cross| / dot, so the
+ * test is dot > 0 and |wi - wj| * dot > |cross| * (1 + wi wj). */
+int orc_related_desitter(const double* coords, int64_t N, int64_t i, int64_t j) {
+  const double* w = coords;
+  const double* x = coords + N;
+  const double* y = coords + 2 * N;
+  const double dot = x[i] * x[j] + y[i] * y[j];
+  const double cr = fabs(x[i] * y[j] - y[i] * x[j]);
+  const double dw = fabs(w[i] - w[j]);
+  const double b = 1.0 + w[i] * w[j];
+  return dot > 0.0 && dw * dot > cr * b;
+}
+
+void orc_link_desitter(const double* coords, int64_t N, uint64_t* bits, int64_t W) {
+  memset(bits, 0, (size_t)N * (size_t)W * sizeof(uint64_t));
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < N; ++i) {
+    uint64_t* row = bits + i * W;
+    for (int64_t k = 0; k < N; ++k) {
+      if (k == i) continue;
+      if (orc_related_desitter(coords, N, i < k ? i : k, i < k ? k : i))
+        row[k >> 6] |= 1ULL << (k & 63);
+    }
+  }
+}
+
 /* Number of chains i < k < j with i~k and k~j, counted through the middle
  * element: sum over k of (#related below k) * (#related above k).  For a
  * transitive relation this equals the sum of m over related pairs. */
