@@ -40,6 +40,36 @@ PEAK = {
 }
 
 
+# HBM traffic per launch of a count kernel on this workload: rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each divided by what the same
+# counter reads per byte of a plain device-to-device copy.  Keyed by the
+# SHA-256 of the kernel's source files when the counters were taken: after
+# any change to them the figure no longer describes the kernel and is
+# reported as null.
+TRAFFIC = {}
+KERNEL_SOURCES = {
+    "k_count_mfma<int8>": ["k_count_mfma.hip", "cs_device.h", "cs_internal.h"],
+    "k_count_mfma<fp4>": ["k_count_mfma.hip", "cs_device.h", "cs_internal.h"],
+    "k_count_pop": ["k_count_pop.hip", "cs_device.h", "cs_internal.h"],
+}
+
+
+def sources_digest(kernel: str) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_1709_03013_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_bytes(kernel: str):
+    t = TRAFFIC.get(kernel)
+    if t is None or t["sources"] != sources_digest(kernel):
+        return None
+    return t["bytes"]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -47,6 +77,7 @@ def log(*a):
 def span_words(bits: np.ndarray, N: int) -> int:
     """W_alg = sum over related pairs i<j of the number of 64-bit words that
     hold columns i+1..j-1 (the words Alg. 5 ANDs and counts)."""
+    log("span_words: counting the span of every related pair of N=%d on the host" % N)
     W = bits.shape[1]
     tot = 0
     rowblk = 1024
@@ -75,13 +106,56 @@ def span_words(bits: np.ndarray, N: int) -> int:
     return tot
 
 
-def run_step(cs, ctx, ev, path):
+def mfma_roofline(N: int, t: float, fp4: bool) -> dict:
+    """Matrix-core count: 2*C(N,3) operations (one multiply and one add per
+    triple i < k < j) in t seconds against the dense peak of its operand type."""
+    ops = 2.0 * math.comb(N, 3)
+    kernel = "k_count_mfma<fp4>" if fp4 else "k_count_mfma<int8>"
+    r = {"bound": "mfma", "achieved": ops / t / 1e12,
+         "peak": (PEAK["fp4_mfma_flops"] if fp4 else PEAK["int8_mfma_tops"]) / 1e12,
+         "unit": "TFLOP/s", "kernel": kernel,
+         "work": "2*C(N,3) operations (multiply + add per triple i<k<j), %s operands"
+                 % ("fp4 e2m1 0/1" if fp4 else "int8 0/1 (an int8 operation counted as a flop)")}
+    r["frac"] = r["achieved"] / r["peak"]
+    r["traffic"] = traffic_bytes(kernel)
+    r["sources"] = sources_digest(kernel)
+    return r
+
+
+def pop_roofline(walg, t: float) -> dict:
+    """Popcount count: 4 int32 VALU operations (2 AND, 2 bit counts) per
+    64-bit word of every related pair's span."""
+    ops = 4.0 * walg if walg else float("nan")
+    r = {"bound": "alu", "achieved": ops / t / 1e12, "peak": PEAK["alu_int32_ops"] / 1e12,
+         "unit": "TOP/s", "kernel": "k_count_pop",
+         "work": "4 int32 ops per 64-bit word of the span of every related pair (W_alg=%s)" % walg}
+    r["frac"] = r["achieved"] / r["peak"]
+    r["traffic"] = traffic_bytes("k_count_pop")
+    r["sources"] = sources_digest("k_count_pop")
+    return r
+
+
+def link_figures(N: int, W: int, link_ms) -> dict:
+    """Link kernel: N*W*8 bytes of matrix written (coordinate reads are
+    N*16 bytes and negligible) per launch."""
+    t = float(np.mean(link_ms)) / 1000.0
+    byt = N * W * 8
+    return {"bound": "hbm", "achieved": byt / t / 1e9, "peak": PEAK["hbm_bytes"] / 1e9,
+            "unit": "GB/s", "frac": byt / t / PEAK["hbm_bytes"], "bytes": byt,
+            "link_ms": {"mean": t * 1000.0, "min": float(np.min(link_ms)),
+                        "median": float(np.median(link_ms))}}
+
+
+def run_step(cs, ctx, ev, stream, path):
+    """One pass of the hot path; ev[0..2] bracket link and count on the
+    library's stream."""
     d, N, seed = WORKLOAD["d"], WORKLOAD["N"], WORKLOAD["seed"]
     s = cs.cs_sprinkle(ctx, d, N, seed)
+    ev[0].record(stream)
     cs.cs_link(ctx, s)
-    ev[0].record(ev[2])
+    ev[1].record(stream)
     n, R, sm = cs.cs_interval_abundances(ctx, s, 3, path)
-    ev[1].record(ev[2])
+    ev[2].record(stream)
     S = cs.cs_bd_action(ctx, s)
     return s, n, R, sm, S
 
@@ -100,12 +174,14 @@ def cpu_baseline(budget_s: float = 12.0):
     pairs = 0
     rows = 0
     t_count = 0.0
+    log("cpu_baseline: oracle link of N=%d done in %.1f s on %d threads" % (N, t_link, nthreads))
     for lo in order:
         t1 = time.time()
         _, R, _ = oracle.count_bits(bits, N, nbins=4, rows=(lo, lo + 64))
         t_count += time.time() - t1
         pairs += R
         rows += 64
+        log("cpu_baseline: rows %d..%d, %.1f s so far" % (lo, lo + 63, t_count))
         if t_count > budget_s:
             break
     return {
@@ -122,9 +198,11 @@ def ensemble(cs, ctx, nsets=512):
     out = {}
     try:
         cs.cs_batch_run(ctx, plan)  # warm-up (graph capture, tuning)
+        log("ensemble: warm-up batch done")
         t0 = time.time()
         res = cs.cs_batch_run(ctx, plan)
         tb = time.time() - t0
+        log("ensemble: batched %d sets in %.3f s" % (nsets, tb))
         out["batched_actions_per_s"] = nsets / tb
         out["batched_s"] = tb
     except cs.CsError as e:
@@ -139,6 +217,7 @@ def ensemble(cs, ctx, nsets=512):
         per.append((list(map(int, n)), R, sm, cs.cs_bd_action(ctx, s)))
         cs.cs_set_free(s)
     tp = time.time() - t0
+    log("ensemble: per-set loop %d sets in %.3f s" % (nsets, tp))
     out["per_set_actions_per_s"] = nsets / tp
     out["per_set_s"] = tp
     if res is not None:
@@ -149,11 +228,11 @@ def ensemble(cs, ctx, nsets=512):
     return out
 
 
-def served(cs, nreq=10000, slots=4, budget_gib=32, load=0.7):
+def served(cs, nreq=10000, slots=4, budget_gib=32.0, load=0.7):
     """Served stream: requests with Poisson arrivals (N log-uniform in
     [512, 32768], d in {2, 4}).  The saturated rate is measured first on a
     burst of the first 1500 requests; the timed run offers all requests at
-    `load` times that rate."""
+    `load` times that rate.  Half the budget may hold resident matrices."""
     import causet_inputs as ci
     plan = ci.request_plan(nreq)
     ctx = cs.cs_create(0, int(budget_gib * 2**30), None)
@@ -180,6 +259,9 @@ def served(cs, nreq=10000, slots=4, budget_gib=32, load=0.7):
                         lat.append(tm[2])
                         del pending[t]
                         done += 1
+                        if done % 1000 == 0:
+                            log("served (%g GiB): %d/%d done, %.1f s" % (budget_gib, done, len(reqs),
+                                                                        time.perf_counter() - t0))
                 if k < len(reqs) and arrivals is not None:
                     time.sleep(max(0.0, min(0.0005, arrivals[k] - (time.perf_counter() - t0))))
             return time.perf_counter() - t0, np.array(lat)
@@ -188,6 +270,7 @@ def served(cs, nreq=10000, slots=4, budget_gib=32, load=0.7):
         cal_n = min(1500, nreq)
         t_cal, _ = drive(reqs[:cal_n], None)
         sat = cal_n / t_cal
+        log("served (%g GiB): saturated %.0f actions/s on a burst of %d" % (budget_gib, sat, cal_n))
         rate = load * sat
         gaps = np.array([a for a, *_ in plan])
         gaps = gaps / gaps[-1] * (nreq / rate)  # rescale the Poisson arrivals to `rate`
@@ -203,13 +286,14 @@ def served(cs, nreq=10000, slots=4, budget_gib=32, load=0.7):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--path", type=int, default=0, help="0 auto, 1 popcount, 2 MFMA")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-span", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-pop", action="store_true", help="skip the one popcount-path count")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers 3 times (calibrates HBM counters)")
     ap.add_argument("--serve-requests", type=int, default=10000)
@@ -238,54 +322,61 @@ def main():
     torch.cuda.init()
     stream = torch.cuda.Stream(device=0)
     ctx = cs.cs_create(0, 0, stream.cuda_stream)
-    ev = [torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True), stream]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
 
     for _ in range(a.warmup):
-        s, *_ = run_step(cs, ctx, ev, a.path)
+        s, *_ = run_step(cs, ctx, ev, stream, a.path)
         cs.cs_set_free(s)
     torch.cuda.synchronize()
-    count_ms = []
+    log("warm-up done (%d steps)" % a.warmup)
+    count_ms, link_ms, step_ms = [], [], []
     t0 = time.perf_counter()
     for k in range(a.steps):
-        s, n, R, sm, S = run_step(cs, ctx, ev, a.path)
-        ev[1].synchronize()
-        count_ms.append(ev[0].elapsed_time(ev[1]))
+        ts = time.perf_counter()
+        s, n, R, sm, S = run_step(cs, ctx, ev, stream, a.path)
+        ev[2].synchronize()
+        step_ms.append((time.perf_counter() - ts) * 1000.0)
+        link_ms.append(ev[0].elapsed_time(ev[1]))
+        count_ms.append(ev[1].elapsed_time(ev[2]))
         if k + 1 < a.steps:
             cs.cs_set_free(s)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1000.0 / a.steps
-    log("step %.1f ms, count %s ms" % (ms_step, ["%.1f" % x for x in count_ms]))
+    log("step %.1f ms, count %s ms, link %s ms" % (ms_step, ["%.1f" % x for x in count_ms],
+                                                  ["%.2f" % x for x in link_ms]))
 
     N = WORKLOAD["N"]
+    W = cs.cs_row_words(N)
     path_used = cs.cs_set_count_path(s)
     t_count = float(np.mean(count_ms)) / 1000.0
     if path_used in (2, 3):
-        ops = 2.0 * math.comb(N, 3)
-        fp4 = path_used == 3
-        roof = {"bound": "mfma", "achieved": ops / t_count / 1e12,
-                "peak": (PEAK["fp4_mfma_flops"] if fp4 else PEAK["int8_mfma_tops"]) / 1e12,
-                "unit": "TFLOP/s" if fp4 else "TOP/s",
-                "kernel": "k_count_mfma<fp4>" if fp4 else "k_count_mfma<int8>",
-                "work": "2*C(N,3) ops (one multiply-add per triple i<k<j), %s operands" % ("fp4 e2m1 0/1" if fp4 else "int8 0/1")}
+        roof = mfma_roofline(N, t_count, path_used == 3)
     else:
-        if a.no_span:
-            walg = None
-        else:
-            bits = cs.cs_get_bitset(ctx, s)
-            walg = span_words(bits, N)
-            del bits
-        ops = 4.0 * walg if walg else float("nan")
-        roof = {"bound": "alu", "achieved": ops / t_count / 1e12, "peak": PEAK["alu_int32_ops"] / 1e12,
-                "unit": "TOP/s", "kernel": "k_count_pop",
-                "work": "4 int32 ops per 64-bit word of the span of every related pair (W_alg=%s)" % walg}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["count_ms"] = float(np.mean(count_ms))
+        walg = None if a.no_span else span_words(cs.cs_get_bitset(ctx, s), N)
+        roof = pop_roofline(walg, t_count)
+    roof["count_ms"] = {"mean": float(np.mean(count_ms)), "min": float(np.min(count_ms)),
+                        "median": float(np.median(count_ms))}
+    kernels = {"link": link_figures(N, W, link_ms)}
+    if not a.no_pop and path_used != 1:
+        # the popcount kernel on the same matrix, once, for its ALU fraction
+        ev[1].record(stream)
+        n1, R1, sm1 = cs.cs_interval_abundances(ctx, s, 3, 1)
+        ev[2].record(stream)
+        ev[2].synchronize()
+        t_pop = ev[1].elapsed_time(ev[2]) / 1000.0
+        walg = None if a.no_span else span_words(cs.cs_get_bitset(ctx, s), N)
+        kernels["pop"] = pop_roofline(walg, t_pop)
+        kernels["pop"]["count_ms"] = t_pop * 1000.0
+        kernels["pop"]["equals_mfma"] = (list(n1) == list(n) and R1 == R and sm1 == sm)
+        log("popcount path on the same set: %.1f ms" % (t_pop * 1000.0))
     cs.cs_set_free(s)
 
     ens = None if a.no_batch else ensemble(cs, ctx)
-    srv = None if a.no_serve else served(cs, a.serve_requests)
+    srv = None
+    if not a.no_serve:
+        srv = {"unbound_32gib": served(cs, a.serve_requests, budget_gib=32.0),
+               "bound_1gib": served(cs, a.serve_requests, budget_gib=1.0)}
     cpu = None if a.no_cpu else cpu_baseline()
     cs.cs_destroy(ctx)
 
@@ -300,6 +391,7 @@ def main():
                    "N": N, "d": 2, "related_pairs": R, "abundances": [int(x) for x in n],
                    "action": S, "count_path": {1: "pop", 2: "mfma_int8", 3: "mfma_fp4"}[path_used]},
         "roofline": roof,
+        "kernels": kernels,
         "cpu_baseline": cpu,
         "ensemble": ens,
         "served": srv,

@@ -90,6 +90,29 @@ uint64_t cs_bytes_in_use(const cs_ctx* ctx);
 cs_status cs_sprinkle(cs_ctx* ctx, int d, int64_t N, uint64_t seed,
                       cs_set** out);
 
+/* Coordinate manifold of a set (cs_set_manifold). */
+enum { CS_MANIFOLD_DIAMOND = 0, CS_MANIFOLD_DESITTER = 1 };
+
+/* Sprinkle N elements into the (1+1) de Sitter slab of Sec. 6.1 (Eq. 9),
+ * ds^2 = sec^2(eta)(-deta^2 + dtheta^2), eta in [-eta0, eta0], theta on the
+ * circle, and sort them by time.  The volume element is dw dtheta with
+ * w = tan(eta), so w is uniform on [-w0, w0], w0 = tan(eta0) (host libm).
+ * Element c, attempt a = 0..63: Philox4x64-10 at counter (c, a, 0, 0), key
+ * (seed, 5); w = (2 dbl(r0) - 1) w0, direction x = 2 dbl(r1) - 1,
+ * y = 2 dbl(r2) - 1, accepted iff 0 < x*x + y*y < 1 (after 64 rejections
+ * (x, y) = (1, 0); w is the last attempt's).  Sorted by w, then c.
+ * Coordinates: 3 rows (w, x, y); (x, y) is the unnormalised direction of
+ * theta.  The set has d = 2 (2D action weights); cs_link tests
+ * |delta eta| > geodesic angle as dot > 0 and
+ * |w_i - w_j| * dot > |cross| * (1 + w_i w_j).  0 < eta0 < pi/4 (the
+ * tangent test needs |delta eta| < pi/2), else CS_EINVAL. */
+cs_status cs_sprinkle_desitter(cs_ctx* ctx, int64_t N, uint64_t seed, double eta0,
+                               cs_set** out);
+
+/* Manifold (CS_MANIFOLD_*) of a set and its number of coordinate rows
+ * (d for diamonds, 3 for de Sitter, 0 for a set imported as a matrix). */
+cs_status cs_set_manifold(const cs_set* set, int* manifold, int* coord_rows);
+
 /* Import coordinates (host, SoA, d*N doubles) already in a topological
  * order: the caller's order becomes the labels.  The buffer is copied. */
 cs_status cs_set_from_coords(cs_ctx* ctx, int d, int64_t N,
@@ -110,7 +133,8 @@ void cs_set_free(cs_set* set);
 cs_status cs_set_info(const cs_set* set, int* d, int64_t* N, int64_t* W,
                       int* linked);
 
-/* Copy the sorted coordinates (d*N doubles, SoA) and, if orig != NULL, the
+/* Copy the sorted coordinates (rows*N doubles, SoA; rows from
+ * cs_set_manifold) and, if orig != NULL, the
  * generation index of each sorted element, to host memory. */
 cs_status cs_get_coords(cs_ctx* ctx, const cs_set* set, double* coords,
                         int64_t* orig);

@@ -62,6 +62,9 @@ _SIGS = {
     "cs_set_info": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), _i64p, _i64p,
                                    ctypes.POINTER(ctypes.c_int)]),
     "cs_get_coords": (ctypes.c_int, [_vp, _vp, _dp, _i64p]),
+    "cs_sprinkle_desitter": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double,
+                                            ctypes.POINTER(_vp)]),
+    "cs_set_manifold": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "cs_get_bitset": (ctypes.c_int, [_vp, _vp, _u64p]),
     "cs_set_bitset_dev": (_vp, [_vp]),
     "cs_set_count_path": (ctypes.c_int, [_vp]),
@@ -149,6 +152,16 @@ def cs_sprinkle(ctx: int, d: int, N: int, seed: int) -> int:
     return h.value
 
 
+CS_MANIFOLD_DIAMOND = 0
+CS_MANIFOLD_DESITTER = 1
+
+
+def cs_sprinkle_desitter(ctx: int, N: int, seed: int, eta0: float) -> int:
+    h = _vp()
+    _check(lib().cs_sprinkle_desitter(ctx, N, seed % 2**64, float(eta0), ctypes.byref(h)))
+    return h.value
+
+
 def cs_set_from_coords(ctx: int, d: int, coords: np.ndarray) -> int:
     c = np.ascontiguousarray(coords, dtype=np.float64)
     N = c.shape[1] if c.ndim == 2 else 0
@@ -185,9 +198,17 @@ def cs_set_info(s: int):
     return d.value, N.value, W.value, bool(linked.value)
 
 
+def cs_set_manifold(s: int):
+    m = ctypes.c_int()
+    rows = ctypes.c_int()
+    _check(lib().cs_set_manifold(s, ctypes.byref(m), ctypes.byref(rows)))
+    return m.value, rows.value
+
+
 def cs_get_coords(ctx: int, s: int):
-    d, N, _, _ = cs_set_info(s)
-    coords = np.zeros((d, N), dtype=np.float64)
+    _, N, _, _ = cs_set_info(s)
+    _, rows = cs_set_manifold(s)
+    coords = np.zeros((rows, N), dtype=np.float64)
     orig = np.zeros(N, dtype=np.int64)
     _check(lib().cs_get_coords(ctx, s, _ptr(coords, _dp), _ptr(orig, _i64p)))
     return coords, orig

@@ -228,14 +228,17 @@ void cs_destroy(cs_ctx* ctx) {
 
 uint64_t cs_bytes_in_use(const cs_ctx* ctx) { return ctx ? ctx->pool.live_bytes : 0; }
 
-static cs_status new_set(cs_ctx* ctx, int d, int64_t N, cs_set** out) {
+static cs_status new_set(cs_ctx* ctx, int d, int64_t N, cs_set** out, int rows = -1,
+                         int manifold = CS_MANIFOLD_DIAMOND) {
   cs_set* s = new cs_set();
   s->ctx = ctx;
   s->d = d;
+  s->rows = rows < 0 ? d : rows;
+  s->manifold = manifold;
   s->N = N;
   s->W = row_words(N);
-  if (N > 0 && d > 0) {
-    s->coords = (double*)ctx->pool.alloc((size_t)N * d * sizeof(double));
+  if (N > 0 && s->rows > 0) {
+    s->coords = (double*)ctx->pool.alloc((size_t)N * s->rows * sizeof(double));
     s->orig = (int64_t*)ctx->pool.alloc((size_t)N * sizeof(int64_t));
     if (!s->coords || !s->orig) {
       cs_set_free(s);
@@ -298,6 +301,42 @@ cs_status cs_sprinkle(cs_ctx* ctx, int d, int64_t N, uint64_t seed, cs_set** out
     }
   }
   *out = s;
+  return CS_OK;
+}
+
+cs_status cs_sprinkle_desitter(cs_ctx* ctx, int64_t N, uint64_t seed, double eta0, cs_set** out) {
+  if (!ctx || !out) return fail(CS_EINVAL, "cs_sprinkle_desitter: NULL argument");
+  *out = nullptr;
+  if (!(eta0 > 0.0 && eta0 < 0.78539816339744830962))
+    return fail(CS_EINVAL, "cs_sprinkle_desitter: eta0 must be in (0, pi/4), got %g", eta0);
+  if (N < 0 || N > ((int64_t)1 << 31)) return fail(CS_EINVAL, "cs_sprinkle_desitter: bad N %lld", (long long)N);
+  (void)hipSetDevice(ctx->device);
+  cs_set* s = nullptr;
+  cs_status rc = new_set(ctx, 2, N, &s, 3, CS_MANIFOLD_DESITTER);
+  if (rc != CS_OK) return rc;
+  if (N > 0) {
+    DevBuf scratch(ctx->pool, sprinkle_desitter_scratch_bytes(N));
+    if (!scratch.p) {
+      cs_set_free(s);
+      return fail(CS_ENOMEM, "cs_sprinkle_desitter: scratch exceeds budget");
+    }
+    hipError_t e = launch_sprinkle_desitter(N, seed, std::tan(eta0), s->coords, s->orig,
+                                            scratch.p, ctx->stream);
+    // finish before the scratch returns to the pool
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+      cs_set_free(s);
+      return hip_fail(e, "de Sitter sprinkle");
+    }
+  }
+  *out = s;
+  return CS_OK;
+}
+
+cs_status cs_set_manifold(const cs_set* s, int* manifold, int* coord_rows) {
+  if (!s) return fail(CS_EINVAL, "cs_set_manifold: NULL set");
+  if (manifold) *manifold = s->manifold;
+  if (coord_rows) *coord_rows = s->rows;
   return CS_OK;
 }
 
@@ -405,7 +444,7 @@ cs_status cs_get_coords(cs_ctx* ctx, const cs_set* s, double* coords, int64_t* o
   (void)hipSetDevice(ctx->device);
   hipError_t e = hipSuccess;
   if (s->N > 0 && coords)
-    e = hipMemcpyAsync(coords, s->coords, (size_t)s->N * s->d * 8, hipMemcpyDeviceToHost, ctx->stream);
+    e = hipMemcpyAsync(coords, s->coords, (size_t)s->N * s->rows * 8, hipMemcpyDeviceToHost, ctx->stream);
   if (e == hipSuccess && s->N > 0 && orig)
     e = hipMemcpyAsync(orig, s->orig, (size_t)s->N * 8, hipMemcpyDeviceToHost, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -436,7 +475,8 @@ cs_status cs_link(cs_ctx* ctx, cs_set* s) {
     if (!s->bits)
       return fail(CS_ENOMEM, "cs_link: matrix of %llu bytes exceeds the HBM budget",
                   (unsigned long long)((size_t)s->N * s->W * 8));
-    hipError_t e = launch_link(s->d, s->N, s->coords, s->bits, s->W, ctx->stream);
+    const int kind = s->manifold == CS_MANIFOLD_DESITTER ? kLinkDeSitter : s->d;
+    hipError_t e = launch_link(kind, s->N, s->coords, s->bits, s->W, ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "link launch");
   }
   s->linked = true;

@@ -47,6 +47,15 @@ hipError_t launch_sprinkle(int d, int64_t N, uint64_t seed, int64_t ncand,
                            double* coords, int64_t* orig, void* scratch,
                            uint64_t* accepted_dev, hipStream_t st);
 
+// (1+1) de Sitter slab: sorted SoA (w = tan eta, x, y), 3*N doubles.
+size_t sprinkle_desitter_scratch_bytes(int64_t N);
+hipError_t launch_sprinkle_desitter(int64_t N, uint64_t seed, double w0, double* coords,
+                                    int64_t* orig, void* scratch, hipStream_t st);
+
+// Link kinds: 2 and 4 = flat diamonds (d rows of coordinates), kLinkDeSitter
+// = the (1+1) de Sitter slab (rows w, x, y).
+constexpr int kLinkDeSitter = 3;
+
 // Link: bits must hold N*W words; every word of every row is written.
 hipError_t launch_link(int d, int64_t N, const double* coords, uint64_t* bits,
                        int64_t W, hipStream_t st);

@@ -62,8 +62,10 @@ struct cs_ctx {
 struct cs_set {
   cs_ctx* ctx = nullptr;
   int d = 0;
+  int manifold = 0;          // CS_MANIFOLD_*
+  int rows = 0;              // coordinate rows: d, or 3 for de Sitter
   int64_t N = 0, W = 0;
-  double* coords = nullptr;  // d*N SoA, sorted
+  double* coords = nullptr;  // rows*N SoA, sorted
   int64_t* orig = nullptr;   // generation index of each sorted element
   uint64_t* bits = nullptr;  // N*W words
   bool linked = false;

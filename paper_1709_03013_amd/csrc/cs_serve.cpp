@@ -47,6 +47,7 @@ struct Request {
   cs_req req{};
   Clock::time_point t_submit, t_admit, t_done;
   bool done = false;
+  int redo = 0;  // 4D: times the acceptance fell short (each doubles the candidates)
   cs_result res{};
 };
 
@@ -130,6 +131,13 @@ static void finish_request(QueueState* q, Slot& s, cs_status st) {
   s.transient.clear();
   if (s.res) {
     s.res->users--;
+    if (st != CS_OK && s.res->users == 0) {
+      // a failed request's matrix is never reused
+      Resident* bad = s.res;
+      q->ctx->pool.release(bad->bits);
+      q->resident_bytes -= bad->bytes;
+      q->resident.remove_if([&](const std::unique_ptr<Resident>& x) { return x.get() == bad; });
+    }
     // keep it resident only while the resident budget allows
     while (q->resident_bytes > q->resident_budget) {
       Resident* victim = nullptr;
@@ -158,7 +166,7 @@ static bool launch_request(QueueState* q, Slot& s, std::shared_ptr<Request> rq, 
   const int64_t W = row_words(N);
   const auto key = std::make_tuple(d, N, rq->req.seed);
   Resident* res = find_resident(q, key);
-  const int64_t ncand = d == 4 ? candidates_4d(N) : N;
+  const int64_t ncand = d == 4 ? candidates_4d(N) << rq->redo : N;
   const size_t need = footprint(d, N, ncand, res == nullptr);
   if (!make_room(q, need)) return false;
   std::vector<void*> tr;
@@ -243,9 +251,15 @@ static void server(QueueState* q) {
       }
       Request& r = *s.rq;
       if (r.req.d == 4 && (int64_t)s.host[6] < r.req.N) {
-        // far tail of the 4D acceptance: redo this request from scratch
+        // far tail of the 4D acceptance: redo this request from scratch with
+        // twice the candidates (the same counters, so the same first N)
         Resident* bad = s.res;
         std::shared_ptr<Request> again = s.rq;
+        if (again->redo >= 7) {
+          finish_request(q, s, CS_EDEVICE);
+          continue;
+        }
+        again->redo++;
         for (void* p : s.transient) ctx->pool.release(p);
         s.transient.clear();
         bad->users--;

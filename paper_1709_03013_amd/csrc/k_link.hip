@@ -14,7 +14,13 @@
 //   4D: dt*dt > (dx*dx + dy*dy) + dz*dz with d* = coordinate of k minus
 //       coordinate of i.  Rounding is sign-symmetric, so this equals the
 //       test written with the earlier element subtracted; dt*dt > 0 implies
-//       dt != 0, so equal times are unrelated.  No fused multiply-add.
+//       dt != 0, so equal times are unrelated.
+//   de Sitter slab (Sec. 6.1), rows (w = tan eta, x, y) with (x, y) an
+//       unnormalised direction: |d eta| > geodesic angle, which for eta0 <
+//       pi/4 reads dot > 0 and |w_i - w_k| * dot > |cross| * (1 + w_i w_k)
+//       (tangent of a difference).  Every operand is exactly symmetric in the
+//       pair (products commute, a - b = -(b - a)).
+// No fused multiply-add anywhere.
 #include "cs_internal.h"
 
 #pragma clang fp contract(off)
@@ -38,6 +44,12 @@ __device__ __forceinline__ bool related_dir(const Pt<D>& a, const Pt<D>& b) {
     if constexpr (DIR == 1) return fwd;
     if constexpr (DIR == 2) return bwd;
     return fwd | bwd;
+  } else if constexpr (D == 3) {
+    const double dot = a.c[1] * b.c[1] + a.c[2] * b.c[2];
+    const double cr = fabs(a.c[1] * b.c[2] - a.c[2] * b.c[1]);
+    const double dw = fabs(a.c[0] - b.c[0]);
+    const double bb = 1.0 + a.c[0] * b.c[0];
+    return (dot > 0.0) & (dw * dot > cr * bb);
   } else {
     const double dt = b.c[0] - a.c[0];
     const double dx = b.c[1] - a.c[1];
@@ -181,6 +193,8 @@ hipError_t launch_link(int d, int64_t N, const double* coords, uint64_t* bits,
   dim3 grid((unsigned)((W + 63) / 64), (unsigned)((N + 63) / 64));
   if (d == 2)
     hipLaunchKernelGGL(k_link<2>, grid, dim3(256), 0, st, coords, N, bits, W);
+  else if (d == kLinkDeSitter)
+    hipLaunchKernelGGL(k_link<3>, grid, dim3(256), 0, st, coords, N, bits, W);
   else
     hipLaunchKernelGGL(k_link<4>, grid, dim3(256), 0, st, coords, N, bits, W);
   return hipGetLastError();

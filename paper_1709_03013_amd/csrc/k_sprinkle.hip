@@ -13,6 +13,13 @@
 //     multiply-add).  The first N accepted in candidate order are the
 //     elements, sorted by (r0>>11, acceptance rank).
 //
+// (1+1) de Sitter slab (Sec. 6.1, Eq. 9): the volume element sec^2(eta)
+//     deta dtheta is dw dtheta with w = tan(eta), so elements are uniform in
+//     w on [-w0, w0] (w0 = tan(eta0)) and in angle.  Element c, attempt a =
+//     0..63, block at counter (c, a, 0, 0), key (seed, 5): w = (2 dbl(r0) - 1)
+//     w0; the direction (x, y) = 2 dbl(r1..r2) - 1 is accepted iff 0 < x*x +
+//     y*y < 1 (after 64 rejections: (1, 0)).  Sorted by (w, c).
+//
 // Sort: each workgroup bitonic-sorts a tile of 2048 records in LDS; every
 // record then finds its global rank as its rank in its own tile plus the
 // number of smaller records in every other tile (binary search), and
@@ -87,6 +94,42 @@ __global__ __launch_bounds__(256) void k_keys2d(int64_t N, uint64_t seed,
   s.k2 = a;
   s.idx = (uint64_t)c;
   recs[c] = s;
+}
+
+// Order-preserving map of a binary64 to uint64 (w is never -0: (2u - 1) is
+// +0 when zero and w0 > 0).
+__device__ __forceinline__ uint64_t order_bits(double w) {
+  const uint64_t b = (uint64_t)__double_as_longlong(w);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__global__ __launch_bounds__(256) void k_keys_desitter(int64_t N, uint64_t seed, double w0,
+                                                       SortRec* __restrict__ recs,
+                                                       double* __restrict__ raw) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= N) return;
+  double w = 0.0, x = 1.0, y = 0.0;
+  for (uint64_t a = 0; a < 64; ++a) {
+    uint64_t r[4] = {(uint64_t)c, a, 0, 0};
+    philox10(r, seed, 5);
+    w = (2.0 * unit53(r[0]) - 1.0) * w0;
+    const double xc = 2.0 * unit53(r[1]) - 1.0;
+    const double yc = 2.0 * unit53(r[2]) - 1.0;
+    const double rr = xc * xc + yc * yc;
+    if (rr > 0.0 && rr < 1.0) {
+      x = xc;
+      y = yc;
+      break;
+    }
+  }
+  SortRec s;
+  s.k1 = order_bits(w);
+  s.k2 = (uint64_t)c;
+  s.idx = (uint64_t)c;
+  recs[c] = s;
+  raw[c] = w;
+  raw[N + c] = x;
+  raw[2 * N + c] = y;
 }
 
 __global__ __launch_bounds__(256) void k_count4d(int64_t ncand, uint64_t seed,
@@ -236,7 +279,7 @@ __device__ __forceinline__ void rank_scatter_one(const SortRec* __restrict__ rec
     coords[rank] = (double)my.k2 * 0x1.0p-53;
     coords[N + rank] = (double)(my.k1 - my.k2) * 0x1.0p-53;
   } else {
-    for (int q = 0; q < 4; ++q) coords[(int64_t)q * N + rank] = raw[(int64_t)q * N + my.idx];
+    for (int q = 0; q < D; ++q) coords[(int64_t)q * N + rank] = raw[(int64_t)q * N + my.idx];
   }
 }
 
@@ -400,6 +443,25 @@ hipError_t launch_sprinkle(int d, int64_t N, uint64_t seed, int64_t ncand,
   else
     hipLaunchKernelGGL(k_rank_scatter<4>, dim3(gN), dim3(256), 0, st, recs, N,
                        raw, coords, orig);
+  return hipGetLastError();
+}
+
+size_t sprinkle_desitter_scratch_bytes(int64_t N) {
+  return align256((size_t)N * sizeof(SortRec)) + align256((size_t)N * 3 * sizeof(double));
+}
+
+hipError_t launch_sprinkle_desitter(int64_t N, uint64_t seed, double w0, double* coords,
+                                    int64_t* orig, void* scratch, hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  char* p = (char*)scratch;
+  SortRec* recs = (SortRec*)p;
+  p += align256((size_t)N * sizeof(SortRec));
+  double* raw = (double*)p;
+  const unsigned gN = (unsigned)((N + 255) / 256);
+  hipLaunchKernelGGL(k_keys_desitter, dim3(gN), dim3(256), 0, st, N, seed, w0, recs, raw);
+  const unsigned ntiles = (unsigned)((N + kSortTile - 1) / kSortTile);
+  hipLaunchKernelGGL(k_tile_sort, dim3(ntiles), dim3(1024), 0, st, recs, N);
+  hipLaunchKernelGGL(k_rank_scatter<3>, dim3(gN), dim3(256), 0, st, recs, N, raw, coords, orig);
   return hipGetLastError();
 }
 
