@@ -1,6 +1,7 @@
 """Benchmark: interval pairs/s and BD actions/s on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--path P] [--no-cpu] [--no-batch]
+                    [--no-serve] [--no-pop] [--no-span] [--no-desitter]
 
 One step = the whole hot path on the 2D flat causal diamond with N = 131072
 elements (seed 3): sprinkle + time sort, link (2 GiB packed matrix), interval
@@ -14,8 +15,19 @@ Also reported on the same line:
     on the library's stream over the timed region;
   * cpu_baseline: the CPU oracle's counting rate on a bounded row sample of
     the same set, on this host's cores;
+  * kernels: the link kernel's HBM rate, and the popcount kernel on the same
+    matrix (once) with its integer-ALU fraction;
   * ensemble: 512 sets (N uniform in [256, 4096], d in {2, 4}) as BD
-    actions/s, batched (one cs_batch_run) vs per-set (a loop of cs_* calls).
+    actions/s, batched (one cs_batch_run) vs per-set (a loop of cs_* calls);
+  * desitter: ten (1+1) de Sitter slabs of 2^15 elements (eta0 = 0.5), the
+    smeared action at eps = 2^-6 against 4 pi tan(eta0);
+  * served: 10,000 queued requests (N log-uniform in [512, 32768]) with
+    Poisson arrivals at 0.7x the saturated rate, p50/p99 latency and
+    actions/s, under a 32 GiB and a 1 GiB budget.
+
+Protocol: W warm-up steps (default 3), then K timed steps (default 5);
+ms_per_step is their mean, count/link kernel times are also given as min and
+median.
 """
 from __future__ import annotations
 
@@ -48,6 +60,8 @@ PEAK = {
 # reported as null.
 TRAFFIC = {}
 KERNEL_SOURCES = {
+    "k_count_mfma_lds<int8>": ["k_count_mfma.hip", "cs_device.h", "cs_internal.h"],
+    "k_count_mfma_lds<fp4>": ["k_count_mfma.hip", "cs_device.h", "cs_internal.h"],
     "k_count_mfma<int8>": ["k_count_mfma.hip", "cs_device.h", "cs_internal.h"],
     "k_count_mfma<fp4>": ["k_count_mfma.hip", "cs_device.h", "cs_internal.h"],
     "k_count_pop": ["k_count_pop.hip", "cs_device.h", "cs_internal.h"],
@@ -110,7 +124,9 @@ def mfma_roofline(N: int, t: float, fp4: bool) -> dict:
     """Matrix-core count: 2*C(N,3) operations (one multiply and one add per
     triple i < k < j) in t seconds against the dense peak of its operand type."""
     ops = 2.0 * math.comb(N, 3)
-    kernel = "k_count_mfma<fp4>" if fp4 else "k_count_mfma<int8>"
+    # the library's kernel shape (CS_MFMA_VARIANT, default 2: LDS-staged, 2x4 waves, 4 stages)
+    lds = int(os.environ.get("CS_MFMA_VARIANT", "2")) >= 2
+    kernel = ("k_count_mfma_lds" if lds else "k_count_mfma") + ("<fp4>" if fp4 else "<int8>")
     r = {"bound": "mfma", "achieved": ops / t / 1e12,
          "peak": (PEAK["fp4_mfma_flops"] if fp4 else PEAK["int8_mfma_tops"]) / 1e12,
          "unit": "TFLOP/s", "kernel": kernel,
@@ -228,6 +244,24 @@ def ensemble(cs, ctx, nsets=512):
     return out
 
 
+def desitter(cs, ctx, N=32768, graphs=10, eta0=0.5, eps=2.0**-6):
+    """The paper's de Sitter experiment (Sec. 6.1): ten (1+1) de Sitter slabs
+    of N elements at eta0, the smeared action with eps, against the
+    continuum value 4 pi tan(eta0)."""
+    S = []
+    t0 = time.time()
+    for g in range(graphs):
+        s = cs.cs_sprinkle_desitter(ctx, N, 1000 + g, eta0)
+        cs.cs_link(ctx, s)
+        S.append(cs.cs_smeared_action(ctx, s, eps))
+        cs.cs_set_free(s)
+    t = time.time() - t0
+    log("desitter: %d graphs of N=%d in %.2f s" % (graphs, N, t))
+    return {"N": N, "graphs": graphs, "eta0": eta0, "eps": eps, "seeds": "1000..%d" % (1000 + graphs - 1),
+            "S_eps_mean": float(np.mean(S)), "S_eps_sd": float(np.std(S, ddof=1)),
+            "S_EH": 4 * math.pi * math.tan(eta0), "graphs_per_s": graphs / t}
+
+
 def served(cs, nreq=10000, slots=4, budget_gib=32.0, load=0.7):
     """Served stream: requests with Poisson arrivals (N log-uniform in
     [512, 32768], d in {2, 4}).  The saturated rate is measured first on a
@@ -294,6 +328,7 @@ def main():
     ap.add_argument("--no-span", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-pop", action="store_true", help="skip the one popcount-path count")
+    ap.add_argument("--no-desitter", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers 3 times (calibrates HBM counters)")
     ap.add_argument("--serve-requests", type=int, default=10000)
@@ -373,6 +408,7 @@ def main():
     cs.cs_set_free(s)
 
     ens = None if a.no_batch else ensemble(cs, ctx)
+    dsx = None if a.no_desitter else desitter(cs, ctx)
     srv = None
     if not a.no_serve:
         srv = {"unbound_32gib": served(cs, a.serve_requests, budget_gib=32.0),
@@ -394,6 +430,7 @@ def main():
         "kernels": kernels,
         "cpu_baseline": cpu,
         "ensemble": ens,
+        "desitter": dsx,
         "served": srv,
     }
     print(json.dumps(rec))

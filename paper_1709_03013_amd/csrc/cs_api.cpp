@@ -191,6 +191,8 @@ cs_status cs_create(cs_ctx** out, int device, uint64_t hbm_budget_bytes, void* h
   if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(CS_EUNSUPPORTED, "cs_create: device is %s, library is built for gfx950", prop.gcnArchName);
+  e = init_count_mfma();
+  if (e != hipSuccess) return hip_fail(e, "count kernel attributes");
   cs_ctx* c = new cs_ctx();
   c->device = device;
   c->num_cu = prop.multiProcessorCount;
@@ -593,7 +595,8 @@ cs_status cs_count_dev(const uint64_t* bits_dev, int64_t N, int64_t stride_words
   hipStream_t st = (hipStream_t)hip_stream;
   const int64_t nrb = num_row_blocks(N);
   const size_t nws = (size_t)(nrb > 0 ? nrb : 1) * (kmax + 3);
-  hipError_t e = launch_fill_u64((uint64_t*)work_dev, 0, nws, st);
+  hipError_t e = init_count_mfma();
+  if (e == hipSuccess) e = launch_fill_u64((uint64_t*)work_dev, 0, nws, st);
   if (e == hipSuccess && N > 1) e = run_count(bits_dev, N, stride_words, kmax, path, (uint64_t*)work_dev, st);
   if (e == hipSuccess) e = launch_reduce_rows((uint64_t*)work_dev, nrb > 0 ? nrb : 1, kmax, stats_dev, st);
   return e == hipSuccess ? CS_OK : hip_fail(e, "cs_count_dev");

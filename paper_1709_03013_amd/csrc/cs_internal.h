@@ -132,6 +132,8 @@ hipError_t launch_batch_sprinkle(const BatchDev& b, hipStream_t st);
 hipError_t launch_batch_link(const BatchDev& b, hipStream_t st);
 hipError_t launch_batch_count_pop(const BatchDev& b, int grid, hipStream_t st);
 hipError_t launch_batch_count_mfma(const BatchDev& b, int grid, hipStream_t st);
+// Once per device before the first count: kernel attributes (LDS limits).
+hipError_t init_count_mfma();
 hipError_t launch_batch_finish(const BatchDev& b, hipStream_t st);
 
 // BD action from abundances (host): exact int64 bracket, one rounding.

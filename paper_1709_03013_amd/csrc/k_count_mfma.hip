@@ -84,6 +84,135 @@ __device__ __forceinline__ v8i spread_fp4(uint32_t D) {
   return f;
 }
 
+// Epilogue of one 256x256 tile.  Lane l holds column j = J0 + 32b + l%32
+// and rows i = I0 + 32a + 8(v/4) + 4(l/32) + v%4 of tile (a, b); the
+// relation bit (i, j) is bit i of row j (all 32 rows of a tile share one word
+// of row j).  In a diagonal tile the bits of rows i >= j are cleared first,
+// so every test below is a plain bit test.  With FULL, pairs that are not
+// counted add to a spare bin kmax+1 so the LDS atomics need no branch.
+template <int TM, int TN, int kThreads, bool FULL, typename Acc>
+__device__ __forceinline__ void mfma_epilogue(const Acc (&acc)[TM][TN], const uint64_t* __restrict__ bits,
+                                              int64_t N, int64_t W, int64_t BI, int64_t BJ,
+                                              int64_t I0, int64_t J0, int kmax,
+                                              uint64_t* __restrict__ rb_stats, uint32_t* lds_hist) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int r32 = lane & 31, g = lane >> 5;
+  uint32_t cnt[4] = {0, 0, 0, 0};
+  uint32_t nrel = 0;
+  uint64_t summ = 0;
+  uint64_t* st = rb_stats + BI * (int64_t)(kmax + 3);
+  const uint32_t lb = (uint32_t)(kmax + 1 < kLdsBins ? kmax + 1 : kLdsBins);
+#pragma unroll
+  for (int b = 0; b < TN; ++b) {
+    const int64_t j = J0 + 32 * b + r32;
+#pragma unroll
+    for (int a = 0; a < TM; ++a) {
+      const int64_t ibase = I0 + 32 * a;
+      const uint64_t rw = j < N ? bits[j * W + (ibase >> 6)] : 0ull;
+      uint32_t r = (uint32_t)(rw >> (ibase & 63));
+      if (BI == BJ) {
+        const int64_t lim = j - ibase;  // rows ri < lim have i < j
+        r &= lim >= 32 ? ~0u : (lim <= 0 ? 0u : ((1u << lim) - 1u));
+      }
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int ri = 8 * (v >> 2) + 4 * g + (v & 3);
+        const bool valid = (r >> ri) & 1u;
+        const uint32_t m = (uint32_t)acc[a][b][v];
+        nrel += valid ? 1u : 0u;
+        summ += valid ? m : 0u;
+        if constexpr (FULL) {
+          atomicAdd(&lds_hist[valid && m < lb ? m : lb], 1u);
+          if (valid && m >= lb && m <= (uint32_t)kmax)
+            atomicAdd((unsigned long long*)&st[m], 1ull);
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) cnt[k] += (valid && m == (uint32_t)k) ? 1u : 0u;
+        }
+      }
+    }
+  }
+  nrel = wave_sum_u32(nrel);
+  summ = wave_sum_u64(summ);
+  if constexpr (!FULL) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cnt[k] = wave_sum_u32(cnt[k]);
+    if (lane < 4) {
+      const uint32_t v = lane == 0 ? cnt[0] : lane == 1 ? cnt[1] : lane == 2 ? cnt[2] : cnt[3];
+      if (v) atomicAdd((unsigned long long*)&st[lane], (unsigned long long)v);
+    }
+  } else {
+    __syncthreads();
+    for (int b = tid; b < (int)lb; b += kThreads) {
+      const uint32_t v = lds_hist[b];
+      if (v) atomicAdd((unsigned long long*)&st[b], (unsigned long long)v);
+    }
+  }
+  if (lane == 0) {
+    if (nrel) atomicAdd((unsigned long long*)&st[kmax + 1], (unsigned long long)nrel);
+    if (summ) atomicAdd((unsigned long long*)&st[kmax + 2], (unsigned long long)summ);
+  }
+}
+
+// One chunk of 4 words (256 columns k) for a wave's TM x TN tiles: xa / xb
+// hold the lane's 16 bytes (words 4c + 2g, 4c + 2g + 1) of its row in every A
+// and B tile; dword q is half q&1 of word 4c + 2g + q/2.  Masks (first and
+// last chunk only), spreading and the MFMAs.
+template <int TM, int TN, bool FP4, typename Acc>
+__device__ __forceinline__ void mfma_chunk(Acc (&acc)[TM][TN], uint32_t (&xa)[TM][4],
+                                           uint32_t (&xb)[TN][4], int64_t I0, int64_t J0,
+                                           int64_t c, bool mask_a, bool mask_b) {
+  const int lane = threadIdx.x & 63;
+  const int r32 = lane & 31, g = lane >> 5;
+  if (mask_a) {
+#pragma unroll
+    for (int t = 0; t < TM; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        xa[t][q] &= (uint32_t)(mask_above(I0 + 32 * t + r32, 4 * c + 2 * g + (q >> 1)) >> (32 * (q & 1)));
+  }
+  if (mask_b) {
+#pragma unroll
+    for (int t = 0; t < TN; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        xb[t][q] &= (uint32_t)(mask_below(J0 + 32 * t + r32, 4 * c + 2 * g + (q >> 1)) >> (32 * (q & 1)));
+  }
+  if constexpr (FP4) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v8i fa[TM], fb[TN];
+#pragma unroll
+      for (int t = 0; t < TM; ++t) fa[t] = spread_fp4(xa[t][q]);
+#pragma unroll
+      for (int t = 0; t < TN; ++t) fb[t] = spread_fp4(xb[t][q]);
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+              fa[a], fb[b], acc[a][b], 4, 4, 0, 127, 0, 127);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        v4i fa[TM], fb[TN];
+#pragma unroll
+        for (int t = 0; t < TM; ++t) fa[t] = spread4(xa[t][q], 4 * h);
+#pragma unroll
+        for (int t = 0; t < TN; ++t) fb[t] = spread4(xb[t][q], 4 * h);
+#pragma unroll
+        for (int a = 0; a < TM; ++a)
+#pragma unroll
+          for (int b = 0; b < TN; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
+      }
+  }
+}
+
 // WM x WN waves over the 256x256 tile; each wave owns (256/WM) x (256/WN)
 // pairs as TM x TN tiles of 32x32.  FP4 selects the e2m1 contraction
 // (v_mfma_scale_f32_32x32x64_f8f6f4, unit scales) instead of int8: one MFMA
@@ -159,52 +288,7 @@ __device__ __forceinline__ void mfma_tile(const uint64_t* __restrict__ bits, int
       xb[t][0] = nbw[t].x; xb[t][1] = nbw[t].y; xb[t][2] = nbw[t].z; xb[t][3] = nbw[t].w;
     }
     load_chunk(c < c1 ? c + 1 : c1);
-    if (mask_a) {
-#pragma unroll
-      for (int t = 0; t < TM; ++t)
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          xa[t][q] &= (uint32_t)(mask_above(I0 + 32 * t + r32, 4 * c + 2 * g + (q >> 1)) >> (32 * (q & 1)));
-    }
-    if (mask_b) {
-#pragma unroll
-      for (int t = 0; t < TN; ++t)
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          xb[t][q] &= (uint32_t)(mask_below(J0 + 32 * t + r32, 4 * c + 2 * g + (q >> 1)) >> (32 * (q & 1)));
-    }
-    if constexpr (FP4) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        v8i fa[TM], fb[TN];
-#pragma unroll
-        for (int t = 0; t < TM; ++t) fa[t] = spread_fp4(xa[t][q]);
-#pragma unroll
-        for (int t = 0; t < TN; ++t) fb[t] = spread_fp4(xb[t][q]);
-#pragma unroll
-        for (int a = 0; a < TM; ++a)
-#pragma unroll
-          for (int b = 0; b < TN; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                fa[a], fb[b], acc[a][b], 4, 4, 0, 127, 0, 127);
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          v4i fa[TM], fb[TN];
-#pragma unroll
-          for (int t = 0; t < TM; ++t) fa[t] = spread4(xa[t][q], 4 * h);
-#pragma unroll
-          for (int t = 0; t < TN; ++t) fb[t] = spread4(xb[t][q], 4 * h);
-#pragma unroll
-          for (int a = 0; a < TM; ++a)
-#pragma unroll
-            for (int b = 0; b < TN; ++b)
-              acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
-        }
-    }
+    mfma_chunk<TM, TN, FP4>(acc, xa, xb, I0, J0, c, mask_a, mask_b);
   };
   load_chunk(c0);
   if (c0 == c1) {
@@ -215,67 +299,138 @@ __device__ __forceinline__ void mfma_tile(const uint64_t* __restrict__ bits, int
     step(c1, false, true);
   }
 
-  // Epilogue.  Lane l holds column j = J0 + 32b + l%32 and rows
-  // i = I0 + 32a + 8(v/4) + 4(l/32) + v%4 of tile (a, b); the relation bit
-  // (i, j) is bit i of row j (all 32 rows of a tile share one word of row j).
-  // In a diagonal tile the bits of rows i >= j are cleared first, so every
-  // test below is a plain bit test.  With FULL, pairs that are not counted
-  // add to a spare bin kmax+1 so the LDS atomics need no branch.
-  uint32_t cnt[4] = {0, 0, 0, 0};
-  uint32_t nrel = 0;
-  uint64_t summ = 0;
-  uint64_t* st = rb_stats + BI * (int64_t)(kmax + 3);
-  const uint32_t lb = (uint32_t)(kmax + 1 < kLdsBins ? kmax + 1 : kLdsBins);
+  mfma_epilogue<TM, TN, kThreads, FULL>(acc, bits, N, W, BI, BJ, I0, J0, kmax, rb_stats, lds_hist);
+}
+
+// ---- LDS-staged form -------------------------------------------------------
+// The chunks of the tile's 512 rows (256 A rows of block BI, 256 B rows of
+// block BJ) travel global -> LDS by 16-byte LDS DMA loads (no registers, no
+// VALU), S chunks in flight, so the wait for memory overlaps S-1 chunks of
+// MFMA work.  A stage is 1024 slots of 16 bytes: slot 2r + s holds half
+// s ^ ((r >> 2) & 1) of stage row r (rows 0..255 = A, 256..511 = B), so the
+// 8 lanes of one ds_read_b128 pass (8 consecutive rows, one half) cover all
+// 32 banks, and two neighbouring lanes of a DMA load read the two halves of
+// one row (32 contiguous bytes).  Each row is read from global memory once
+// per workgroup instead of once per wave that uses it.
+constexpr int kStageBytes = 512 * 32;
+
+__device__ __forceinline__ uint32_t stage_slot(int r, int half) {
+  return (uint32_t)(2 * r + (half ^ ((r >> 2) & 1)));
+}
+
+template <int WM, int WN, bool FULL, bool FP4, int S>
+__device__ __forceinline__ void mfma_tile_lds(const uint64_t* __restrict__ bits, int64_t N,
+                                              int64_t W, int64_t BI, int64_t BJ, int kmax,
+                                              uint64_t* __restrict__ rb_stats,
+                                              uint32_t* lds_hist, char* stages) {
+  constexpr int kWaves = WM * WN;
+  constexpr int kThreads = 64 * kWaves;
+  constexpr int TM = kBT / WM / 32;
+  constexpr int TN = kBT / WN / 32;
+  constexpr int L = 1024 / kThreads;  // DMA loads per wave per chunk
+  static_assert(L * kThreads == 1024 && S >= 2 && L * (S - 2) <= 63, "bad stage shape");
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int r32 = lane & 31, g = lane >> 5;
+  const int64_t I0 = BI * kBT + (wave / WN) * (32 * TM);
+  const int64_t J0 = BJ * kBT + (wave % WN) * (32 * TN);
+
+  // DMA load p of this wave fills slots (wave*L + p)*64 + lane of a stage:
+  // stage row r = slot/2 (A if r < 256), half from the swizzle.  Global
+  // address = uniform block base + 32c + a 32-bit lane offset; rows past N
+  // read the block's first row (their pairs are dropped in the epilogue).
+  const char* gbase[L];
+  uint32_t goff[L];
 #pragma unroll
-  for (int b = 0; b < TN; ++b) {
-    const int64_t j = J0 + 32 * b + r32;
-#pragma unroll
-    for (int a = 0; a < TM; ++a) {
-      const int64_t ibase = I0 + 32 * a;
-      const uint64_t rw = j < N ? bits[j * W + (ibase >> 6)] : 0ull;
-      uint32_t r = (uint32_t)(rw >> (ibase & 63));
-      if (BI == BJ) {
-        const int64_t lim = j - ibase;  // rows ri < lim have i < j
-        r &= lim >= 32 ? ~0u : (lim <= 0 ? 0u : ((1u << lim) - 1u));
-      }
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int ri = 8 * (v >> 2) + 4 * g + (v & 3);
-        const bool valid = (r >> ri) & 1u;
-        const uint32_t m = (uint32_t)acc[a][b][v];
-        nrel += valid ? 1u : 0u;
-        summ += valid ? m : 0u;
-        if constexpr (FULL) {
-          atomicAdd(&lds_hist[valid && m < lb ? m : lb], 1u);
-          if (valid && m >= lb && m <= (uint32_t)kmax)
-            atomicAdd((unsigned long long*)&st[m], 1ull);
-        } else {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) cnt[k] += (valid && m == (uint32_t)k) ? 1u : 0u;
-        }
-      }
-    }
+  for (int p = 0; p < L; ++p) {
+    const int slot0 = (wave * L + p) * 64;  // uniform
+    const bool side_b = slot0 >= 512;
+    const int slot = slot0 + lane;
+    const int r = (slot >> 1) & 255;
+    const int half = (slot & 1) ^ ((r >> 2) & 1);
+    const int64_t blk = side_b ? BJ : BI;
+    gbase[p] = (const char*)(bits + blk * kBT * W);
+    const bool valid = blk * kBT + r < N;
+    goff[p] = (uint32_t)((valid ? (int64_t)r * W * 8 : 0) + 16 * half);
   }
-  nrel = wave_sum_u32(nrel);
-  summ = wave_sum_u64(summ);
-  if constexpr (!FULL) {
+  typedef __attribute__((address_space(3))) void* lds_ptr;
+  typedef __attribute__((address_space(1))) const void* global_ptr;
+  auto issue = [&](int64_t c, int st) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) cnt[k] = wave_sum_u32(cnt[k]);
-    if (lane < 4) {
-      const uint32_t v = lane == 0 ? cnt[0] : lane == 1 ? cnt[1] : lane == 2 ? cnt[2] : cnt[3];
-      if (v) atomicAdd((unsigned long long*)&st[lane], (unsigned long long)v);
+    for (int p = 0; p < L; ++p)
+      __builtin_amdgcn_global_load_lds((global_ptr)(gbase[p] + c * 32 + goff[p]),
+                                       (lds_ptr)(stages + st * kStageBytes + (wave * L + p) * 1024),
+                                       16, 0, 0);
+  };
+  // LDS byte offsets of this lane's 16 bytes in every A and B tile.
+  uint32_t aoff[TM], boff[TN];
+#pragma unroll
+  for (int t = 0; t < TM; ++t)
+    aoff[t] = 16u * stage_slot((wave / WN) * (32 * TM) + 32 * t + r32, g);
+#pragma unroll
+  for (int t = 0; t < TN; ++t)
+    boff[t] = 16u * stage_slot(256 + (wave % WN) * (32 * TN) + 32 * t + r32, g);
+
+  using Acc = typename std::conditional<FP4, v16f, v16i>::type;
+  Acc acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[a][b][v] = 0;
+
+  const int64_t c0 = BI, c1 = BJ;
+  // Prologue: chunks c0 .. c0+S-2 (clamped to c1: a clamped load refills a
+  // stage nobody reads again, so every wave always has the same number of
+  // loads in flight and the wait count below is a constant).
+#pragma unroll
+  for (int k = 0; k < S - 1; ++k) issue(c0 + k <= c1 ? c0 + k : c1, k);
+  int st = 0;
+  for (int64_t c = c0; c <= c1; ++c) {
+    // This wave's loads of chunk c are done when at most L*(S-2) (chunks
+    // c+1 .. c+S-2) are outstanding; the barrier makes every wave's part of
+    // the stage visible and guarantees that every wave finished reading the
+    // stage about to be refilled (its LDS reads completed before it came).
+    asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(L * (S - 2)) : "memory");
+    const int64_t cn = c + S - 1 <= c1 ? c + S - 1 : c1;
+    issue(cn, st == 0 ? S - 1 : st - 1);
+    const char* sb = stages + st * kStageBytes;
+    uint32_t xa[TM][4], xb[TN][4];
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+      const uint4 v = *(const uint4*)(sb + aoff[t]);
+      xa[t][0] = v.x; xa[t][1] = v.y; xa[t][2] = v.z; xa[t][3] = v.w;
     }
-  } else {
+#pragma unroll
+    for (int t = 0; t < TN; ++t) {
+      const uint4 v = *(const uint4*)(sb + boff[t]);
+      xb[t][0] = v.x; xb[t][1] = v.y; xb[t][2] = v.z; xb[t][3] = v.w;
+    }
+    mfma_chunk<TM, TN, FP4>(acc, xa, xb, I0, J0, c, c == c0, c == c1);
+    st = st == S - 1 ? 0 : st + 1;
+  }
+  // No LDS DMA may still be writing when the stages are reused or freed.
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+
+  mfma_epilogue<TM, TN, kThreads, FULL>(acc, bits, N, W, BI, BJ, I0, J0, kmax, rb_stats, lds_hist);
+}
+
+template <int WM, int WN, bool FULL, bool FP4, int S>
+__global__ __launch_bounds__(64 * WM * WN, 1) void k_count_mfma_lds(
+    const uint64_t* __restrict__ bits, int64_t N, int64_t W, int64_t nb,
+    int kmax, uint64_t* __restrict__ rb_stats) {
+  extern __shared__ __align__(16) char smem[];  // S stages, then (FULL) lb+1 bins
+  uint32_t* lds_hist = (uint32_t*)(smem + S * kStageBytes);
+  int64_t BI, BJ;
+  tri_tile_longest_first((int64_t)blockIdx.x, nb, &BI, &BJ);
+  if constexpr (FULL) {
+    const int lb = kmax + 1 < kLdsBins ? kmax + 1 : kLdsBins;
+    for (int b = threadIdx.x; b <= lb; b += 64 * WM * WN) lds_hist[b] = 0;
     __syncthreads();
-    for (int b = tid; b < (int)lb; b += kThreads) {
-      const uint32_t v = lds_hist[b];
-      if (v) atomicAdd((unsigned long long*)&st[b], (unsigned long long)v);
-    }
   }
-  if (lane == 0) {
-    if (nrel) atomicAdd((unsigned long long*)&st[kmax + 1], (unsigned long long)nrel);
-    if (summ) atomicAdd((unsigned long long*)&st[kmax + 2], (unsigned long long)summ);
-  }
+  mfma_tile_lds<WM, WN, FULL, FP4, S>(bits, N, W, BI, BJ, kmax, rb_stats, lds_hist, smem);
 }
 
 template <int WM, int WN, bool FULL, bool FP4>
@@ -295,7 +450,9 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void k_count_mfma(
 
 // Batched, persistent: each workgroup takes (set, BI, BJ) items from a device
 // queue (longest first) until it is empty.
+template <bool LDS>
 __global__ __launch_bounds__(512, 1) void k_batch_count_mfma(BatchDev b) {
+  extern __shared__ __align__(16) char smem[];  // LDS form: 4 stages
   __shared__ uint32_t item_sh;
   for (;;) {
     const uint32_t mine = next_item(&b.queue_heads[1]);
@@ -307,8 +464,12 @@ __global__ __launch_bounds__(512, 1) void k_batch_count_mfma(BatchDev b) {
     int64_t set, BI, BJ;
     unpack_item(b.mfma_items[it], &set, &BI, &BJ);
     const BatchSet bs = b.sets[set];
-    mfma_tile<2, 4, false>(b.bits + bs.bits_off, bs.N, bs.W, BI, BJ, 3, b.stats + bs.stats_off,
-                           nullptr);
+    if constexpr (LDS)
+      mfma_tile_lds<2, 4, false, false, 4>(b.bits + bs.bits_off, bs.N, bs.W, BI, BJ, 3,
+                                           b.stats + bs.stats_off, nullptr, smem);
+    else
+      mfma_tile<2, 4, false>(b.bits + bs.bits_off, bs.N, bs.W, BI, BJ, 3, b.stats + bs.stats_off,
+                             nullptr);
   }
 }
 
@@ -330,35 +491,102 @@ hipError_t launch_variant(const uint64_t* bits, int64_t N, int64_t W, int kmax,
   return hipGetLastError();
 }
 
+template <int WM, int WN, bool FP4, int S>
+hipError_t launch_lds_variant(const uint64_t* bits, int64_t N, int64_t W, int kmax,
+                              uint64_t* rb_stats, hipStream_t st) {
+  const int64_t nb = (N + kBT - 1) / kBT;
+  const int64_t ntiles = nb * (nb + 1) / 2;
+  if (ntiles > 0x7fffffffLL) return hipErrorInvalidValue;
+  const dim3 block(64 * WM * WN);
+  const size_t stage_bytes = (size_t)S * kStageBytes;
+  if (kmax <= 3) {
+    hipLaunchKernelGGL((k_count_mfma_lds<WM, WN, false, FP4, S>), dim3((unsigned)ntiles), block,
+                       stage_bytes, st, bits, N, W, nb, kmax, rb_stats);
+  } else {
+    const size_t lds = stage_bytes +
+                       (size_t)((kmax + 1 < kLdsBins ? kmax + 1 : kLdsBins) + 1) * sizeof(uint32_t);
+    hipLaunchKernelGGL((k_count_mfma_lds<WM, WN, true, FP4, S>), dim3((unsigned)ntiles), block, lds,
+                       st, bits, N, W, nb, kmax, rb_stats);
+  }
+  return hipGetLastError();
+}
+
+template <bool FP4>
+hipError_t launch_by_variant(int v, const uint64_t* bits, int64_t N, int64_t W, int kmax,
+                             uint64_t* rb_stats, hipStream_t st) {
+  switch (v) {
+    case 0: return launch_variant<2, 2, FP4>(bits, N, W, kmax, rb_stats, st);
+    case 1: return launch_variant<2, 4, FP4>(bits, N, W, kmax, rb_stats, st);
+    case 2: return launch_lds_variant<2, 4, FP4, 4>(bits, N, W, kmax, rb_stats, st);
+    case 3: return launch_lds_variant<2, 2, FP4, 4>(bits, N, W, kmax, rb_stats, st);
+    case 4: return launch_lds_variant<2, 4, FP4, 3>(bits, N, W, kmax, rb_stats, st);
+    default: return launch_lds_variant<2, 2, FP4, 3>(bits, N, W, kmax, rb_stats, st);
+  }
+}
+
 }  // namespace
 
-// 0: 2x2 waves of 128x128 pairs, 1 (default, faster on MI355X): 2x4 waves of
-// 128x64 pairs
+// Kernel shape: 0 = 2x2 waves of 128x128 pairs, 1 = 2x4 waves of 128x64
+// pairs (both loading operands straight to registers, one chunk ahead);
+// 2..5 = the LDS-staged form with 2x4 / 2x2 waves and 4 / 3 stages.  The
+// default, 2, was the fastest on MI355X for both operand types (2D N=2^17:
+// int8 209 ms vs 224 ms for 1; fp4 136 ms vs 176 ms).  The environment
+// variable CS_MFMA_VARIANT overrides it for timing.
 static int mfma_variant() {
-  static int v = [] {
-    const char* e = getenv("CS_MFMA_VARIANT");
-    return e ? atoi(e) : 1;
-  }();
-  return v;
+  const char* e = getenv("CS_MFMA_VARIANT");
+  return e ? atoi(e) : 2;
 }
 
 hipError_t launch_count_mfma(const uint64_t* bits, int64_t N, int64_t W, int kmax,
                              uint64_t* rb_stats, hipStream_t st) {
   static_assert(kBT == kRowBlock, "block tile must equal the stats row block");
   if (N <= 1) return hipSuccess;
-  if (mfma_variant() == 1) return launch_variant<2, 4, false>(bits, N, W, kmax, rb_stats, st);
-  return launch_variant<2, 2, false>(bits, N, W, kmax, rb_stats, st);
+  return launch_by_variant<false>(mfma_variant(), bits, N, W, kmax, rb_stats, st);
 }
 
 hipError_t launch_count_mfma_fp4(const uint64_t* bits, int64_t N, int64_t W, int kmax,
                                  uint64_t* rb_stats, hipStream_t st) {
   if (N <= 1) return hipSuccess;
-  return launch_variant<2, 4, true>(bits, N, W, kmax, rb_stats, st);
+  return launch_by_variant<true>(mfma_variant(), bits, N, W, kmax, rb_stats, st);
+}
+
+namespace {
+template <int WM, int WN, bool FP4, int S>
+hipError_t set_lds_limits() {
+  const int stages = S * kStageBytes;
+  const int full = stages + (kLdsBins + 1) * (int)sizeof(uint32_t);
+  hipError_t e = hipFuncSetAttribute((const void*)k_count_mfma_lds<WM, WN, false, FP4, S>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, stages);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_count_mfma_lds<WM, WN, true, FP4, S>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, full);
+  return e;
+}
+}  // namespace
+
+// Dynamic LDS limits of the LDS-staged kernels (above the 64 KiB default).
+hipError_t init_count_mfma() {
+  hipError_t e = hipFuncSetAttribute((const void*)k_batch_count_mfma<true>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 4 * kStageBytes);
+  if (e == hipSuccess) e = set_lds_limits<2, 4, false, 4>();
+  if (e == hipSuccess) e = set_lds_limits<2, 2, false, 4>();
+  if (e == hipSuccess) e = set_lds_limits<2, 4, false, 3>();
+  if (e == hipSuccess) e = set_lds_limits<2, 2, false, 3>();
+  if (e == hipSuccess) e = set_lds_limits<2, 4, true, 4>();
+  if (e == hipSuccess) e = set_lds_limits<2, 2, true, 4>();
+  if (e == hipSuccess) e = set_lds_limits<2, 4, true, 3>();
+  if (e == hipSuccess) e = set_lds_limits<2, 2, true, 3>();
+  return e;
 }
 
 hipError_t launch_batch_count_mfma(const BatchDev& b, int grid, hipStream_t st) {
   if (b.n_mfma <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_batch_count_mfma, dim3((unsigned)grid), dim3(512), 0, st, b);
+  if (mfma_variant() >= 2) {
+    const size_t lds = 4 * (size_t)kStageBytes;
+    hipLaunchKernelGGL(k_batch_count_mfma<true>, dim3((unsigned)grid), dim3(512), lds, st, b);
+  } else {
+    hipLaunchKernelGGL(k_batch_count_mfma<false>, dim3((unsigned)grid), dim3(512), 0, st, b);
+  }
   return hipGetLastError();
 }
 

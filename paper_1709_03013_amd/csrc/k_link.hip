@@ -21,6 +21,8 @@
 //       (tangent of a difference).  Every operand is exactly symmetric in the
 //       pair (products commute, a - b = -(b - a)).
 // No fused multiply-add anywhere.
+#include <cstdlib>
+
 #include "cs_internal.h"
 
 #pragma clang fp contract(off)
@@ -33,15 +35,17 @@ struct Pt {
   double c[D];
 };
 
-// Relation of two elements (Sec. 1.1, strict).  DIR: 0 = either order (the
-// diagonal 64x64 block), 1 = a before b (columns after the rows), 2 = b
-// before a.  Bitwise & and | keep the test free of branches.
+// Relation of a (the row, wave-uniform) to b (this lane's column) over the
+// wave, as a 64-bit lane mask (Sec. 1.1, strict).  DIR: 0 = either order
+// (the diagonal 64x64 block), 1 = a before b (columns after the rows), 2 = b
+// before a.  Each comparison goes straight to a lane mask (no booleans in
+// VGPRs) and the masks are combined with scalar ANDs.
 template <int D, int DIR>
-__device__ __forceinline__ bool related_dir(const Pt<D>& a, const Pt<D>& b) {
+__device__ __forceinline__ uint64_t related_mask(const Pt<D>& a, const Pt<D>& b) {
   if constexpr (D == 2) {
-    const bool fwd = (a.c[0] < b.c[0]) & (a.c[1] < b.c[1]);
-    const bool bwd = (b.c[0] < a.c[0]) & (b.c[1] < a.c[1]);
+    const uint64_t fwd = __ballot(a.c[0] < b.c[0]) & __ballot(a.c[1] < b.c[1]);
     if constexpr (DIR == 1) return fwd;
+    const uint64_t bwd = __ballot(b.c[0] < a.c[0]) & __ballot(b.c[1] < a.c[1]);
     if constexpr (DIR == 2) return bwd;
     return fwd | bwd;
   } else if constexpr (D == 3) {
@@ -49,7 +53,7 @@ __device__ __forceinline__ bool related_dir(const Pt<D>& a, const Pt<D>& b) {
     const double cr = fabs(a.c[1] * b.c[2] - a.c[2] * b.c[1]);
     const double dw = fabs(a.c[0] - b.c[0]);
     const double bb = 1.0 + a.c[0] * b.c[0];
-    return (dot > 0.0) & (dw * dot > cr * bb);
+    return __ballot(dot > 0.0) & __ballot(dw * dot > cr * bb);
   } else {
     const double dt = b.c[0] - a.c[0];
     const double dx = b.c[1] - a.c[1];
@@ -57,26 +61,31 @@ __device__ __forceinline__ bool related_dir(const Pt<D>& a, const Pt<D>& b) {
     const double dz = b.c[3] - a.c[3];
     const double tt = dt * dt;
     const double xx = dx * dx, yy = dy * dy, zz = dz * dz;
-    return tt > (xx + yy) + zz;
+    return __ballot(tt > (xx + yy) + zz);
   }
 }
 
 // 64 relation words of one column word: lane r ends with word (i0 + r, w).
+// The row's coordinates are LDS broadcasts; each row's word is the wave's
+// compare mask, written into lane r with v_writelane.
 template <int D, int DIR>
 __device__ __forceinline__ uint64_t link_word(const double (*rowc)[64], const Pt<D>& pk,
-                                              bool kval) {
-  const int lane = threadIdx.x & 63;
-  uint64_t my = 0;
-#pragma unroll 16
+                                              uint64_t kmask) {
+  int lo = 0, hi = 0;
+#pragma unroll 8
   for (int r = 0; r < 64; ++r) {
     Pt<D> pi;
 #pragma unroll
     for (int q = 0; q < D; ++q) pi.c[q] = rowc[q][r];
-    const bool rel = kval & related_dir<D, DIR>(pi, pk);
-    const uint64_t m = __ballot(rel);
-    my = lane == r ? m : my;
+    const uint64_t m = kmask & related_mask<D, DIR>(pi, pk);
+    const int mlo = (int)(uint32_t)m, mhi = (int)(uint32_t)(m >> 32);
+    // the lane select goes through M0 (one SGPR operand per VOP3 on gfx9)
+    asm("s_mov_b32 m0, %4\n\tv_writelane_b32 %0, %2, m0\n\tv_writelane_b32 %1, %3, m0"
+        : "+v"(lo), "+v"(hi)
+        : "s"(mlo), "s"(mhi), "s"(r)
+        : "m0");
   }
-  return my;
+  return (uint64_t)(uint32_t)lo | ((uint64_t)(uint32_t)hi << 32);
 }
 
 // One 64-row x 64-word tile of the matrix, rows i0.., words w0.. (256 threads).
@@ -105,16 +114,17 @@ __device__ __forceinline__ void link_tile(const double* __restrict__ coords, int
     if (w < W) {
       const int64_t k = w * 64 + lane;
       const bool kval = k < N;
+      const uint64_t kmask = __ballot(kval);
       const int64_t kk = kval ? k : 0;
       Pt<D> pk;
 #pragma unroll
       for (int q = 0; q < D; ++q) pk.c[q] = coords[(int64_t)q * N + kk];
       if (w * 64 >= i0 + 64)
-        my = link_word<D, 1>(rowc, pk, kval);
+        my = link_word<D, 1>(rowc, pk, kmask);
       else if (w * 64 + 64 <= i0)
-        my = link_word<D, 2>(rowc, pk, kval);
+        my = link_word<D, 2>(rowc, pk, kmask);
       else
-        my = link_word<D, 0>(rowc, pk, kval);
+        my = link_word<D, 0>(rowc, pk, kmask);
     }
     tile[lane][wloc] = my;
   }
