@@ -209,7 +209,6 @@ static cs_status build_plan(cs_ctx* ctx, BatchPlan* p) {
   const size_t o_link = take(link_items.size() * 8);
   const size_t o_pop = take(pop.size() * 8);
   const size_t o_mfma = take(mfma.size() * 8);
-  const size_t o_heads = take(2 * sizeof(uint32_t));
   const size_t o_res = take((size_t)nsets * sizeof(cs_result));
   p->arena_bytes = off;
   p->arena = ctx->pool.alloc(off);
@@ -236,7 +235,6 @@ static cs_status build_plan(cs_ctx* ctx, BatchPlan* p) {
   dv.n_pop = (int64_t)pop.size();
   dv.mfma_items = (const uint64_t*)(A + o_mfma);
   dv.n_mfma = (int64_t)mfma.size();
-  dv.queue_heads = (uint32_t*)(A + o_heads);
   dv.results = (cs_result*)(A + o_res);
   dv.c4 = 4.0 / std::sqrt(6.0);
 
@@ -267,7 +265,6 @@ static cs_status build_plan(cs_ctx* ctx, BatchPlan* p) {
   e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return hip_fail(e, "cs_batch_run: begin capture");
   hipError_t le = launch_fill_u64(dv.stats, 0, (size_t)s_off, st);
-  if (le == hipSuccess) le = launch_fill_u64((uint64_t*)dv.queue_heads, 0, 1, st);
   if (le == hipSuccess) le = launch_batch_sprinkle(dv, st);
   if (le == hipSuccess) le = launch_batch_link(dv, st);
   if (le == hipSuccess) le = launch_batch_count_mfma(dv, p->mfma_grid, st);

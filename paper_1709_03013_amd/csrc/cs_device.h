@@ -20,6 +20,34 @@ __device__ __forceinline__ void tri_tile_longest_first(int64_t t, int64_t nb,
   *bj = off + (nb - q);
 }
 
+// XCD-aware order of the same tiles.  Workgroup ids are dealt to the 8 XCDs
+// round robin (id mod 8), and each XCD has its own L2.  Tiles are grouped
+// into 8x8 super-tiles (row blocks 8sa..8sa+7, column blocks 8sb..8sb+7),
+// the super-tiles ordered longest first; all 64 tiles of super-tile g get
+// ids congruent to g mod 8, so they run on one XCD, 32 at a time, and share
+// its L2: the tiles running together read the rows of 4 row blocks and 8
+// column blocks instead of 32 + 32.  Returns false for the padding ids
+// (below the diagonal or past the last block), which do no work.
+__device__ __forceinline__ bool tile_xcd_grouped(int64_t id, int64_t nb, int64_t* bi,
+                                                 int64_t* bj) {
+  const int64_t nbs = (nb + 7) / 8;
+  const int64_t x = id & 7, r = id >> 9, t = (id >> 3) & 63;
+  const int64_t g = 8 * r + x;
+  if (g >= nbs * (nbs + 1) / 2) return false;
+  int64_t sa, sb;
+  tri_tile_longest_first(g, nbs, &sa, &sb);
+  *bi = 8 * sa + (t >> 3);
+  *bj = 8 * sb + (t & 7);
+  return *bi <= *bj && *bj < nb;
+}
+
+// Number of workgroup ids tile_xcd_grouped needs for nb blocks.
+__host__ __device__ inline int64_t xcd_grouped_ids(int64_t nb) {
+  const int64_t nbs = (nb + 7) / 8;
+  const int64_t ns = nbs * (nbs + 1) / 2;
+  return (ns + 7) / 8 * 512;
+}
+
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -40,15 +68,15 @@ __device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t c) {
   return r;
 }
 
-// Next work item of a persistent workgroup's queue, the same value in every
-// lane.  Every lane issues the atomic but only lane 0 adds 1, so lane 0 gets
-// the head before its own increment whatever order the lanes are applied in;
-// there is no lane-dependent branch, so the compiler cannot let lanes leave
-// a persistent loop in different iterations.  (Kernels using this are built
-// with the atomic combiner off, which would reintroduce such a branch.)
-__device__ __forceinline__ uint32_t next_item(uint32_t* head) {
-  const uint32_t v = atomicAdd(head, threadIdx.x == 0 ? 1u : 0u);
-  return __builtin_amdgcn_readlane(v, 0);
+// Work item of a persistent workgroup in round k: items are sorted longest
+// first and dealt in snake order (round k goes left to right when k is
+// even, right to left when odd), so every workgroup gets a similar mix of
+// long and short items.  A static schedule: no queue, no atomics, and the
+// loop bound is uniform, so every lane leaves the loop in the same
+// iteration.
+__device__ __forceinline__ int64_t snake_item(int64_t k) {
+  const int64_t G = gridDim.x, w = blockIdx.x;
+  return k * G + ((k & 1) ? G - 1 - w : w);
 }
 
 }  // namespace cs

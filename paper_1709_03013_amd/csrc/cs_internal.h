@@ -123,7 +123,6 @@ struct BatchDev {
   const uint64_t* link_items;  int64_t n_link;     // (set, row tile, word tile)
   const uint64_t* pop_items;   int64_t n_pop;      // (set, bi, bj), 64-row blocks
   const uint64_t* mfma_items;  int64_t n_mfma;     // (set, BI, BJ), 256-row blocks
-  uint32_t* queue_heads;                           // [0] pop, [1] mfma
   cs_result* results;
   double c4;                                       // 4/sqrt(6), rounded once on the host
 };

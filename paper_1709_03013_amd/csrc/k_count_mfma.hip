@@ -84,13 +84,82 @@ __device__ __forceinline__ v8i spread_fp4(uint32_t D) {
   return f;
 }
 
+// Weighted spreading.  The k order only has to be the same for A and B;
+// the value each set bit stands for may differ between them as long as the
+// product is one constant.  Class r of D (bits r, r+8, r+16, r+24 for int8;
+// bits r, r+4, ... for fp4) keeps the same k slots as above, but A leaves
+// most classes where they are (one AND) and B moves them so that every
+// product is 64 (int8: 2^r * 2^(6-r); the count is acc >> 6, exact since
+// 64(N-2) < 2^31) or 1.0 (fp4: 0.5*2, 1*1, 2*0.5).  Per 32 bits this takes
+// 9 (A) + 15 (B) int8 ops instead of 30, and 5 (A) + 7 (B) fp4 ops
+// instead of 14.
+__device__ __forceinline__ v4i spread4_wa(uint32_t D, int h) {
+  const uint32_t M = 0x01010101u;
+  v4i f;
+  if (h == 0) {
+    f[0] = (int)(D & M);
+    f[1] = (int)(D & (M << 1));
+    f[2] = (int)(D & (M << 2));
+    f[3] = (int)(D & (M << 3));
+  } else {
+    f[0] = (int)(D & (M << 4));
+    f[1] = (int)(D & (M << 5));
+    f[2] = (int)(D & (M << 6));
+    f[3] = (int)((D >> 7) & M);  // class 7 at bit 0 (bit 7 is the sign)
+  }
+  return f;
+}
+
+__device__ __forceinline__ v4i spread4_wb(uint32_t D, int h) {
+  const uint32_t M = 0x01010101u;
+  v4i f;
+  if (h == 0) {
+    f[0] = (int)((D << 6) & (M << 6));
+    f[1] = (int)((D << 4) & (M << 5));
+    f[2] = (int)((D << 2) & (M << 4));
+    f[3] = (int)(D & (M << 3));
+  } else {
+    f[0] = (int)((D >> 2) & (M << 2));
+    f[1] = (int)((D >> 4) & (M << 1));
+    f[2] = (int)((D >> 6) & M);
+    f[3] = (int)((D >> 1) & (M << 6));
+  }
+  return f;
+}
+
+__device__ __forceinline__ v8i spread_fp4_wa(uint32_t D) {
+  v8i f;
+  f[0] = (int)(D & 0x11111111u);         // 0.5
+  f[1] = (int)(D & 0x22222222u);         // 1.0
+  f[2] = (int)(D & 0x44444444u);         // 2.0
+  f[3] = (int)((D >> 2) & 0x22222222u);  // 1.0
+  f[4] = 0;
+  f[5] = 0;
+  f[6] = 0;
+  f[7] = 0;
+  return f;
+}
+
+__device__ __forceinline__ v8i spread_fp4_wb(uint32_t D) {
+  v8i f;
+  f[0] = (int)((D << 2) & 0x44444444u);  // 2.0
+  f[1] = (int)(D & 0x22222222u);         // 1.0
+  f[2] = (int)((D >> 2) & 0x11111111u);  // 0.5
+  f[3] = (int)((D >> 2) & 0x22222222u);  // 1.0
+  f[4] = 0;
+  f[5] = 0;
+  f[6] = 0;
+  f[7] = 0;
+  return f;
+}
+
 // Epilogue of one 256x256 tile.  Lane l holds column j = J0 + 32b + l%32
 // and rows i = I0 + 32a + 8(v/4) + 4(l/32) + v%4 of tile (a, b); the
 // relation bit (i, j) is bit i of row j (all 32 rows of a tile share one word
 // of row j).  In a diagonal tile the bits of rows i >= j are cleared first,
 // so every test below is a plain bit test.  With FULL, pairs that are not
 // counted add to a spare bin kmax+1 so the LDS atomics need no branch.
-template <int TM, int TN, int kThreads, bool FULL, typename Acc>
+template <int TM, int TN, int kThreads, bool FULL, int SHIFT, typename Acc>
 __device__ __forceinline__ void mfma_epilogue(const Acc (&acc)[TM][TN], const uint64_t* __restrict__ bits,
                                               int64_t N, int64_t W, int64_t BI, int64_t BJ,
                                               int64_t I0, int64_t J0, int kmax,
@@ -119,7 +188,7 @@ __device__ __forceinline__ void mfma_epilogue(const Acc (&acc)[TM][TN], const ui
       for (int v = 0; v < 16; ++v) {
         const int ri = 8 * (v >> 2) + 4 * g + (v & 3);
         const bool valid = (r >> ri) & 1u;
-        const uint32_t m = (uint32_t)acc[a][b][v];
+        const uint32_t m = (uint32_t)acc[a][b][v] >> SHIFT;
         nrel += valid ? 1u : 0u;
         summ += valid ? m : 0u;
         if constexpr (FULL) {
@@ -159,7 +228,7 @@ __device__ __forceinline__ void mfma_epilogue(const Acc (&acc)[TM][TN], const ui
 // hold the lane's 16 bytes (words 4c + 2g, 4c + 2g + 1) of its row in every A
 // and B tile; dword q is half q&1 of word 4c + 2g + q/2.  Masks (first and
 // last chunk only), spreading and the MFMAs.
-template <int TM, int TN, bool FP4, typename Acc>
+template <int TM, int TN, bool FP4, bool WEIGHTED, typename Acc>
 __device__ __forceinline__ void mfma_chunk(Acc (&acc)[TM][TN], uint32_t (&xa)[TM][4],
                                            uint32_t (&xb)[TN][4], int64_t I0, int64_t J0,
                                            int64_t c, bool mask_a, bool mask_b) {
@@ -184,9 +253,9 @@ __device__ __forceinline__ void mfma_chunk(Acc (&acc)[TM][TN], uint32_t (&xa)[TM
     for (int q = 0; q < 4; ++q) {
       v8i fa[TM], fb[TN];
 #pragma unroll
-      for (int t = 0; t < TM; ++t) fa[t] = spread_fp4(xa[t][q]);
+      for (int t = 0; t < TM; ++t) fa[t] = WEIGHTED ? spread_fp4_wa(xa[t][q]) : spread_fp4(xa[t][q]);
 #pragma unroll
-      for (int t = 0; t < TN; ++t) fb[t] = spread_fp4(xb[t][q]);
+      for (int t = 0; t < TN; ++t) fb[t] = WEIGHTED ? spread_fp4_wb(xb[t][q]) : spread_fp4(xb[t][q]);
 #pragma unroll
       for (int a = 0; a < TM; ++a)
 #pragma unroll
@@ -201,15 +270,79 @@ __device__ __forceinline__ void mfma_chunk(Acc (&acc)[TM][TN], uint32_t (&xa)[TM
       for (int h = 0; h < 2; ++h) {
         v4i fa[TM], fb[TN];
 #pragma unroll
-        for (int t = 0; t < TM; ++t) fa[t] = spread4(xa[t][q], 4 * h);
+        for (int t = 0; t < TM; ++t) fa[t] = WEIGHTED ? spread4_wa(xa[t][q], h) : spread4(xa[t][q], 4 * h);
 #pragma unroll
-        for (int t = 0; t < TN; ++t) fb[t] = spread4(xb[t][q], 4 * h);
+        for (int t = 0; t < TN; ++t) fb[t] = WEIGHTED ? spread4_wb(xb[t][q], h) : spread4(xb[t][q], 4 * h);
 #pragma unroll
         for (int a = 0; a < TM; ++a)
 #pragma unroll
           for (int b = 0; b < TN; ++b)
             acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
       }
+  }
+}
+
+// The same chunk, software-pipelined: the weighted spreading of step s+1
+// (a step = one MFMA per tile pair: a dword q for fp4, a (q, h) half for
+// int8) is computed while the MFMAs of step s run, and the scheduler is told
+// to interleave them (one MFMA, then a few VALU instructions), so that a
+// wave keeps the matrix core busy while its own VALU work proceeds.
+template <int TM, int TN, bool FP4, typename Acc>
+__device__ __forceinline__ void mfma_chunk_pipelined(Acc (&acc)[TM][TN], uint32_t (&xa)[TM][4],
+                                                     uint32_t (&xb)[TN][4], int64_t I0, int64_t J0,
+                                                     int64_t c, bool mask_a, bool mask_b) {
+  const int lane = threadIdx.x & 63;
+  const int r32 = lane & 31, g = lane >> 5;
+  if (mask_a) {
+#pragma unroll
+    for (int t = 0; t < TM; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        xa[t][q] &= (uint32_t)(mask_above(I0 + 32 * t + r32, 4 * c + 2 * g + (q >> 1)) >> (32 * (q & 1)));
+  }
+  if (mask_b) {
+#pragma unroll
+    for (int t = 0; t < TN; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        xb[t][q] &= (uint32_t)(mask_below(J0 + 32 * t + r32, 4 * c + 2 * g + (q >> 1)) >> (32 * (q & 1)));
+  }
+  constexpr int kSteps = FP4 ? 4 : 8;
+  constexpr int kValu = FP4 ? 5 : 6;  // VALU instructions placed after each MFMA
+  using Op = typename std::conditional<FP4, v8i, v4i>::type;
+  Op fa[2][TM], fb[2][TN];
+  auto spread = [&](int s, int buf) {
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+      if constexpr (FP4) fa[buf][t] = spread_fp4_wa(xa[t][s]);
+      else fa[buf][t] = spread4_wa(xa[t][s >> 1], s & 1);
+    }
+#pragma unroll
+    for (int t = 0; t < TN; ++t) {
+      if constexpr (FP4) fb[buf][t] = spread_fp4_wb(xb[t][s]);
+      else fb[buf][t] = spread4_wb(xb[t][s >> 1], s & 1);
+    }
+  };
+  spread(0, 0);
+#pragma unroll
+  for (int s = 0; s < kSteps; ++s) {
+    const int cur = s & 1;
+    if (s + 1 < kSteps) spread(s + 1, cur ^ 1);
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int b = 0; b < TN; ++b) {
+        if constexpr (FP4)
+          acc[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa[cur][a], fb[cur][b], acc[a][b],
+                                                                     4, 4, 0, 127, 0, 127);
+        else
+          acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[cur][a], fb[cur][b], acc[a][b], 0, 0, 0);
+      }
+#pragma unroll
+    for (int k = 0; k < TM * TN; ++k) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);      // one MFMA
+      __builtin_amdgcn_sched_group_barrier(0x002, kValu, 0);  // then VALU work
+    }
   }
 }
 
@@ -288,7 +421,7 @@ __device__ __forceinline__ void mfma_tile(const uint64_t* __restrict__ bits, int
       xb[t][0] = nbw[t].x; xb[t][1] = nbw[t].y; xb[t][2] = nbw[t].z; xb[t][3] = nbw[t].w;
     }
     load_chunk(c < c1 ? c + 1 : c1);
-    mfma_chunk<TM, TN, FP4>(acc, xa, xb, I0, J0, c, mask_a, mask_b);
+    mfma_chunk<TM, TN, FP4, false>(acc, xa, xb, I0, J0, c, mask_a, mask_b);
   };
   load_chunk(c0);
   if (c0 == c1) {
@@ -299,7 +432,7 @@ __device__ __forceinline__ void mfma_tile(const uint64_t* __restrict__ bits, int
     step(c1, false, true);
   }
 
-  mfma_epilogue<TM, TN, kThreads, FULL>(acc, bits, N, W, BI, BJ, I0, J0, kmax, rb_stats, lds_hist);
+  mfma_epilogue<TM, TN, kThreads, FULL, 0>(acc, bits, N, W, BI, BJ, I0, J0, kmax, rb_stats, lds_hist);
 }
 
 // ---- LDS-staged form -------------------------------------------------------
@@ -318,7 +451,7 @@ __device__ __forceinline__ uint32_t stage_slot(int r, int half) {
   return (uint32_t)(2 * r + (half ^ ((r >> 2) & 1)));
 }
 
-template <int WM, int WN, bool FULL, bool FP4, int S>
+template <int WM, int WN, bool FULL, bool FP4, int S, bool WEIGHTED, bool PIPE = false>
 __device__ __forceinline__ void mfma_tile_lds(const uint64_t* __restrict__ bits, int64_t N,
                                               int64_t W, int64_t BI, int64_t BJ, int kmax,
                                               uint64_t* __restrict__ rb_stats,
@@ -408,29 +541,38 @@ __device__ __forceinline__ void mfma_tile_lds(const uint64_t* __restrict__ bits,
       const uint4 v = *(const uint4*)(sb + boff[t]);
       xb[t][0] = v.x; xb[t][1] = v.y; xb[t][2] = v.z; xb[t][3] = v.w;
     }
-    mfma_chunk<TM, TN, FP4>(acc, xa, xb, I0, J0, c, c == c0, c == c1);
+    if constexpr (PIPE)
+      mfma_chunk_pipelined<TM, TN, FP4>(acc, xa, xb, I0, J0, c, c == c0, c == c1);
+    else
+      mfma_chunk<TM, TN, FP4, WEIGHTED>(acc, xa, xb, I0, J0, c, c == c0, c == c1);
     st = st == S - 1 ? 0 : st + 1;
   }
   // No LDS DMA may still be writing when the stages are reused or freed.
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 
-  mfma_epilogue<TM, TN, kThreads, FULL>(acc, bits, N, W, BI, BJ, I0, J0, kmax, rb_stats, lds_hist);
+  mfma_epilogue<TM, TN, kThreads, FULL, ((WEIGHTED || PIPE) && !FP4) ? 6 : 0>(acc, bits, N, W, BI, BJ, I0, J0,
+                                                                   kmax, rb_stats, lds_hist);
 }
 
-template <int WM, int WN, bool FULL, bool FP4, int S>
+template <int WM, int WN, bool FULL, bool FP4, int S, bool WEIGHTED, bool PIPE, bool GROUPED>
 __global__ __launch_bounds__(64 * WM * WN, 1) void k_count_mfma_lds(
     const uint64_t* __restrict__ bits, int64_t N, int64_t W, int64_t nb,
     int kmax, uint64_t* __restrict__ rb_stats) {
   extern __shared__ __align__(16) char smem[];  // S stages, then (FULL) lb+1 bins
   uint32_t* lds_hist = (uint32_t*)(smem + S * kStageBytes);
   int64_t BI, BJ;
-  tri_tile_longest_first((int64_t)blockIdx.x, nb, &BI, &BJ);
+  if constexpr (GROUPED) {
+    if (!tile_xcd_grouped((int64_t)blockIdx.x, nb, &BI, &BJ)) return;  // whole workgroup
+  } else {
+    tri_tile_longest_first((int64_t)blockIdx.x, nb, &BI, &BJ);
+  }
   if constexpr (FULL) {
     const int lb = kmax + 1 < kLdsBins ? kmax + 1 : kLdsBins;
     for (int b = threadIdx.x; b <= lb; b += 64 * WM * WN) lds_hist[b] = 0;
     __syncthreads();
   }
-  mfma_tile_lds<WM, WN, FULL, FP4, S>(bits, N, W, BI, BJ, kmax, rb_stats, lds_hist, smem);
+  mfma_tile_lds<WM, WN, FULL, FP4, S, WEIGHTED, PIPE>(bits, N, W, BI, BJ, kmax, rb_stats, lds_hist,
+                                                      smem);
 }
 
 template <int WM, int WN, bool FULL, bool FP4>
@@ -448,24 +590,19 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void k_count_mfma(
   mfma_tile<WM, WN, FULL, FP4>(bits, N, W, BI, BJ, kmax, rb_stats, lds_hist);
 }
 
-// Batched, persistent: each workgroup takes (set, BI, BJ) items from a device
-// queue (longest first) until it is empty.
+// Batched, persistent: each workgroup takes (set, BI, BJ) items, sorted
+// longest first, in snake order until none is left.
 template <bool LDS>
 __global__ __launch_bounds__(512, 1) void k_batch_count_mfma(BatchDev b) {
   extern __shared__ __align__(16) char smem[];  // LDS form: 4 stages
-  __shared__ uint32_t item_sh;
-  for (;;) {
-    const uint32_t mine = next_item(&b.queue_heads[1]);
-    if (threadIdx.x == 0) item_sh = mine;
-    __syncthreads();
-    const uint32_t it = __builtin_amdgcn_readfirstlane(item_sh);
-    __syncthreads();
-    if ((int64_t)it >= b.n_mfma) break;
+  for (int64_t k = 0;; ++k) {
+    const int64_t it = snake_item(k);
+    if (it >= b.n_mfma) break;
     int64_t set, BI, BJ;
     unpack_item(b.mfma_items[it], &set, &BI, &BJ);
     const BatchSet bs = b.sets[set];
     if constexpr (LDS)
-      mfma_tile_lds<2, 4, false, false, 4>(b.bits + bs.bits_off, bs.N, bs.W, BI, BJ, 3,
+      mfma_tile_lds<2, 4, false, false, 4, false, false>(b.bits + bs.bits_off, bs.N, bs.W, BI, BJ, 3,
                                            b.stats + bs.stats_off, nullptr, smem);
     else
       mfma_tile<2, 4, false>(b.bits + bs.bits_off, bs.N, bs.W, BI, BJ, 3, b.stats + bs.stats_off,
@@ -491,21 +628,22 @@ hipError_t launch_variant(const uint64_t* bits, int64_t N, int64_t W, int kmax,
   return hipGetLastError();
 }
 
-template <int WM, int WN, bool FP4, int S>
+template <int WM, int WN, bool FP4, int S, bool WEIGHTED = false, bool PIPE = false,
+          bool GROUPED = false>
 hipError_t launch_lds_variant(const uint64_t* bits, int64_t N, int64_t W, int kmax,
                               uint64_t* rb_stats, hipStream_t st) {
   const int64_t nb = (N + kBT - 1) / kBT;
-  const int64_t ntiles = nb * (nb + 1) / 2;
+  const int64_t ntiles = GROUPED ? xcd_grouped_ids(nb) : nb * (nb + 1) / 2;
   if (ntiles > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 block(64 * WM * WN);
   const size_t stage_bytes = (size_t)S * kStageBytes;
   if (kmax <= 3) {
-    hipLaunchKernelGGL((k_count_mfma_lds<WM, WN, false, FP4, S>), dim3((unsigned)ntiles), block,
+    hipLaunchKernelGGL((k_count_mfma_lds<WM, WN, false, FP4, S, WEIGHTED, PIPE, GROUPED>), dim3((unsigned)ntiles), block,
                        stage_bytes, st, bits, N, W, nb, kmax, rb_stats);
   } else {
     const size_t lds = stage_bytes +
                        (size_t)((kmax + 1 < kLdsBins ? kmax + 1 : kLdsBins) + 1) * sizeof(uint32_t);
-    hipLaunchKernelGGL((k_count_mfma_lds<WM, WN, true, FP4, S>), dim3((unsigned)ntiles), block, lds,
+    hipLaunchKernelGGL((k_count_mfma_lds<WM, WN, true, FP4, S, WEIGHTED, PIPE, GROUPED>), dim3((unsigned)ntiles), block, lds,
                        st, bits, N, W, nb, kmax, rb_stats);
   }
   return hipGetLastError();
@@ -520,7 +658,13 @@ hipError_t launch_by_variant(int v, const uint64_t* bits, int64_t N, int64_t W, 
     case 2: return launch_lds_variant<2, 4, FP4, 4>(bits, N, W, kmax, rb_stats, st);
     case 3: return launch_lds_variant<2, 2, FP4, 4>(bits, N, W, kmax, rb_stats, st);
     case 4: return launch_lds_variant<2, 4, FP4, 3>(bits, N, W, kmax, rb_stats, st);
-    default: return launch_lds_variant<2, 2, FP4, 3>(bits, N, W, kmax, rb_stats, st);
+    case 5: return launch_lds_variant<2, 2, FP4, 3>(bits, N, W, kmax, rb_stats, st);
+    case 6: return launch_lds_variant<2, 4, FP4, 4, true>(bits, N, W, kmax, rb_stats, st);
+    case 7: return launch_lds_variant<2, 2, FP4, 3, true>(bits, N, W, kmax, rb_stats, st);
+    case 8: return launch_lds_variant<2, 4, FP4, 4, true, true>(bits, N, W, kmax, rb_stats, st);
+    case 9: return launch_lds_variant<2, 2, FP4, 3, true, true>(bits, N, W, kmax, rb_stats, st);
+    case 10: return launch_lds_variant<2, 4, FP4, 4, true, false, true>(bits, N, W, kmax, rb_stats, st);
+    default: return launch_lds_variant<2, 4, FP4, 4, true, true, true>(bits, N, W, kmax, rb_stats, st);
   }
 }
 
@@ -528,7 +672,10 @@ hipError_t launch_by_variant(int v, const uint64_t* bits, int64_t N, int64_t W, 
 
 // Kernel shape: 0 = 2x2 waves of 128x128 pairs, 1 = 2x4 waves of 128x64
 // pairs (both loading operands straight to registers, one chunk ahead);
-// 2..5 = the LDS-staged form with 2x4 / 2x2 waves and 4 / 3 stages.  The
+// 2..5 = the LDS-staged form with 2x4 / 2x2 waves and 4 / 3 stages; 6, 7 =
+// 2x4 waves, 4 stages / 2x2 waves, 3 stages with the weighted spreading; 8,
+// 9 = the same, software-pipelined with interleaved MFMA and VALU; 10, 11 =
+// 6 and 8 with the XCD-grouped tile order.  The
 // default, 2, was the fastest on MI355X for both operand types (2D N=2^17:
 // int8 209 ms vs 224 ms for 1; fp4 136 ms vs 176 ms).  The environment
 // variable CS_MFMA_VARIANT overrides it for timing.
@@ -551,15 +698,18 @@ hipError_t launch_count_mfma_fp4(const uint64_t* bits, int64_t N, int64_t W, int
 }
 
 namespace {
-template <int WM, int WN, bool FP4, int S>
+template <int WM, int WN, bool FP4, int S, bool WEIGHTED = false, bool PIPE = false,
+          bool GROUPED = false>
 hipError_t set_lds_limits() {
   const int stages = S * kStageBytes;
   const int full = stages + (kLdsBins + 1) * (int)sizeof(uint32_t);
-  hipError_t e = hipFuncSetAttribute((const void*)k_count_mfma_lds<WM, WN, false, FP4, S>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, stages);
+  hipError_t e = hipFuncSetAttribute(
+      (const void*)k_count_mfma_lds<WM, WN, false, FP4, S, WEIGHTED, PIPE, GROUPED>,
+      hipFuncAttributeMaxDynamicSharedMemorySize, stages);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_count_mfma_lds<WM, WN, true, FP4, S>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, full);
+    e = hipFuncSetAttribute(
+        (const void*)k_count_mfma_lds<WM, WN, true, FP4, S, WEIGHTED, PIPE, GROUPED>,
+        hipFuncAttributeMaxDynamicSharedMemorySize, full);
   return e;
 }
 }  // namespace
@@ -576,6 +726,18 @@ hipError_t init_count_mfma() {
   if (e == hipSuccess) e = set_lds_limits<2, 2, true, 4>();
   if (e == hipSuccess) e = set_lds_limits<2, 4, true, 3>();
   if (e == hipSuccess) e = set_lds_limits<2, 2, true, 3>();
+  if (e == hipSuccess) e = set_lds_limits<2, 4, false, 4, true>();
+  if (e == hipSuccess) e = set_lds_limits<2, 2, false, 3, true>();
+  if (e == hipSuccess) e = set_lds_limits<2, 4, true, 4, true>();
+  if (e == hipSuccess) e = set_lds_limits<2, 2, true, 3, true>();
+  if (e == hipSuccess) e = set_lds_limits<2, 4, false, 4, true, true>();
+  if (e == hipSuccess) e = set_lds_limits<2, 2, false, 3, true, true>();
+  if (e == hipSuccess) e = set_lds_limits<2, 4, true, 4, true, true>();
+  if (e == hipSuccess) e = set_lds_limits<2, 2, true, 3, true, true>();
+  if (e == hipSuccess) e = set_lds_limits<2, 4, false, 4, true, false, true>();
+  if (e == hipSuccess) e = set_lds_limits<2, 4, true, 4, true, false, true>();
+  if (e == hipSuccess) e = set_lds_limits<2, 4, false, 4, true, true, true>();
+  if (e == hipSuccess) e = set_lds_limits<2, 4, true, 4, true, true, true>();
   return e;
 }
 

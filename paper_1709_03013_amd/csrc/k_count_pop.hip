@@ -166,15 +166,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
   pop_tile<FULL>(bits, N, W, bi, bj, kmax, rb_stats, lds_hist, sI, sJ);
 }
 
-// Batched, persistent: each 64-lane workgroup takes (set, bi, bj) items from
-// a device queue (longest first) until it is empty.
+// Batched, persistent: each 64-lane workgroup takes (set, bi, bj) items,
+// sorted longest first, in snake order until none is left.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_batch_count_pop(
     BatchDev b) {
   __shared__ uint64_t sI[kChunk][64];
   __shared__ uint64_t sJ[kChunk][64];
-  for (;;) {
-    const uint32_t it = next_item(&b.queue_heads[0]);
-    if ((int64_t)it >= b.n_pop) break;
+  for (int64_t k = 0;; ++k) {
+    const int64_t it = snake_item(k);
+    if (it >= b.n_pop) break;
     int64_t set, bi, bj;
     unpack_item(b.pop_items[it], &set, &bi, &bj);
     const BatchSet bs = b.sets[set];
