@@ -124,8 +124,9 @@ def mfma_roofline(N: int, t: float, fp4: bool) -> dict:
     """Matrix-core count: 2*C(N,3) operations (one multiply and one add per
     triple i < k < j) in t seconds against the dense peak of its operand type."""
     ops = 2.0 * math.comb(N, 3)
-    # the library's kernel shape (CS_MFMA_VARIANT, default 2: LDS-staged, 2x4 waves, 4 stages)
-    lds = int(os.environ.get("CS_MFMA_VARIANT", "2")) >= 2
+    # the library's kernel shape (CS_MFMA_VARIANT, default 12: LDS-staged, 2x4 waves,
+    # 4 stages, weighted spreading, XCD-grouped tile order, unscaled fp4 encoding)
+    lds = int(os.environ.get("CS_MFMA_VARIANT", "12")) >= 2
     kernel = ("k_count_mfma_lds" if lds else "k_count_mfma") + ("<fp4>" if fp4 else "<int8>")
     r = {"bound": "mfma", "achieved": ops / t / 1e12,
          "peak": (PEAK["fp4_mfma_flops"] if fp4 else PEAK["int8_mfma_tops"]) / 1e12,

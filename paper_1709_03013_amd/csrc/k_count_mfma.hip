@@ -84,6 +84,17 @@ __device__ __forceinline__ v8i spread_fp4(uint32_t D) {
   return f;
 }
 
+// FP4 contraction of one 32x32 tile over 64 k.  Unit scales (E8M0 127) use
+// the scaled encoding; scale operands of 0 make the compiler emit the
+// unscaled instruction (UNSCALED), whose products are the same.
+template <bool UNSCALED>
+__device__ __forceinline__ v16f mma_fp4(const v8i& a, const v8i& b, const v16f& c) {
+  if constexpr (UNSCALED)
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 4, 4, 0, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 4, 4, 0, 127, 0, 127);
+}
+
 // Weighted spreading.  The k order only has to be the same for A and B;
 // the value each set bit stands for may differ between them as long as the
 // product is one constant.  Class r of D (bits r, r+8, r+16, r+24 for int8;
@@ -228,7 +239,7 @@ __device__ __forceinline__ void mfma_epilogue(const Acc (&acc)[TM][TN], const ui
 // hold the lane's 16 bytes (words 4c + 2g, 4c + 2g + 1) of its row in every A
 // and B tile; dword q is half q&1 of word 4c + 2g + q/2.  Masks (first and
 // last chunk only), spreading and the MFMAs.
-template <int TM, int TN, bool FP4, bool WEIGHTED, typename Acc>
+template <int TM, int TN, bool FP4, bool WEIGHTED, bool UNSCALED = false, typename Acc>
 __device__ __forceinline__ void mfma_chunk(Acc (&acc)[TM][TN], uint32_t (&xa)[TM][4],
                                            uint32_t (&xb)[TN][4], int64_t I0, int64_t J0,
                                            int64_t c, bool mask_a, bool mask_b) {
@@ -260,8 +271,7 @@ __device__ __forceinline__ void mfma_chunk(Acc (&acc)[TM][TN], uint32_t (&xa)[TM
       for (int a = 0; a < TM; ++a)
 #pragma unroll
         for (int b = 0; b < TN; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-              fa[a], fb[b], acc[a][b], 4, 4, 0, 127, 0, 127);
+          acc[a][b] = mma_fp4<UNSCALED>(fa[a], fb[b], acc[a][b]);
     }
   } else {
 #pragma unroll
@@ -451,7 +461,8 @@ __device__ __forceinline__ uint32_t stage_slot(int r, int half) {
   return (uint32_t)(2 * r + (half ^ ((r >> 2) & 1)));
 }
 
-template <int WM, int WN, bool FULL, bool FP4, int S, bool WEIGHTED, bool PIPE = false>
+template <int WM, int WN, bool FULL, bool FP4, int S, bool WEIGHTED, bool PIPE = false,
+          bool UNSCALED = false>
 __device__ __forceinline__ void mfma_tile_lds(const uint64_t* __restrict__ bits, int64_t N,
                                               int64_t W, int64_t BI, int64_t BJ, int kmax,
                                               uint64_t* __restrict__ rb_stats,
@@ -544,7 +555,7 @@ __device__ __forceinline__ void mfma_tile_lds(const uint64_t* __restrict__ bits,
     if constexpr (PIPE)
       mfma_chunk_pipelined<TM, TN, FP4>(acc, xa, xb, I0, J0, c, c == c0, c == c1);
     else
-      mfma_chunk<TM, TN, FP4, WEIGHTED>(acc, xa, xb, I0, J0, c, c == c0, c == c1);
+      mfma_chunk<TM, TN, FP4, WEIGHTED, UNSCALED>(acc, xa, xb, I0, J0, c, c == c0, c == c1);
     st = st == S - 1 ? 0 : st + 1;
   }
   // No LDS DMA may still be writing when the stages are reused or freed.
@@ -554,7 +565,8 @@ __device__ __forceinline__ void mfma_tile_lds(const uint64_t* __restrict__ bits,
                                                                    kmax, rb_stats, lds_hist);
 }
 
-template <int WM, int WN, bool FULL, bool FP4, int S, bool WEIGHTED, bool PIPE, bool GROUPED>
+template <int WM, int WN, bool FULL, bool FP4, int S, bool WEIGHTED, bool PIPE, bool GROUPED,
+          bool UNSCALED>
 __global__ __launch_bounds__(64 * WM * WN, 1) void k_count_mfma_lds(
     const uint64_t* __restrict__ bits, int64_t N, int64_t W, int64_t nb,
     int kmax, uint64_t* __restrict__ rb_stats) {
@@ -571,8 +583,8 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void k_count_mfma_lds(
     for (int b = threadIdx.x; b <= lb; b += 64 * WM * WN) lds_hist[b] = 0;
     __syncthreads();
   }
-  mfma_tile_lds<WM, WN, FULL, FP4, S, WEIGHTED, PIPE>(bits, N, W, BI, BJ, kmax, rb_stats, lds_hist,
-                                                      smem);
+  mfma_tile_lds<WM, WN, FULL, FP4, S, WEIGHTED, PIPE, UNSCALED>(bits, N, W, BI, BJ, kmax, rb_stats,
+                                                                lds_hist, smem);
 }
 
 template <int WM, int WN, bool FULL, bool FP4>
@@ -602,7 +614,7 @@ __global__ __launch_bounds__(512, 1) void k_batch_count_mfma(BatchDev b) {
     unpack_item(b.mfma_items[it], &set, &BI, &BJ);
     const BatchSet bs = b.sets[set];
     if constexpr (LDS)
-      mfma_tile_lds<2, 4, false, false, 4, false, false>(b.bits + bs.bits_off, bs.N, bs.W, BI, BJ, 3,
+      mfma_tile_lds<2, 4, false, false, 4, true, false>(b.bits + bs.bits_off, bs.N, bs.W, BI, BJ, 3,
                                            b.stats + bs.stats_off, nullptr, smem);
     else
       mfma_tile<2, 4, false>(b.bits + bs.bits_off, bs.N, bs.W, BI, BJ, 3, b.stats + bs.stats_off,
@@ -629,7 +641,7 @@ hipError_t launch_variant(const uint64_t* bits, int64_t N, int64_t W, int kmax,
 }
 
 template <int WM, int WN, bool FP4, int S, bool WEIGHTED = false, bool PIPE = false,
-          bool GROUPED = false>
+          bool GROUPED = false, bool UNSCALED = false>
 hipError_t launch_lds_variant(const uint64_t* bits, int64_t N, int64_t W, int kmax,
                               uint64_t* rb_stats, hipStream_t st) {
   const int64_t nb = (N + kBT - 1) / kBT;
@@ -638,12 +650,12 @@ hipError_t launch_lds_variant(const uint64_t* bits, int64_t N, int64_t W, int km
   const dim3 block(64 * WM * WN);
   const size_t stage_bytes = (size_t)S * kStageBytes;
   if (kmax <= 3) {
-    hipLaunchKernelGGL((k_count_mfma_lds<WM, WN, false, FP4, S, WEIGHTED, PIPE, GROUPED>), dim3((unsigned)ntiles), block,
+    hipLaunchKernelGGL((k_count_mfma_lds<WM, WN, false, FP4, S, WEIGHTED, PIPE, GROUPED, UNSCALED>), dim3((unsigned)ntiles), block,
                        stage_bytes, st, bits, N, W, nb, kmax, rb_stats);
   } else {
     const size_t lds = stage_bytes +
                        (size_t)((kmax + 1 < kLdsBins ? kmax + 1 : kLdsBins) + 1) * sizeof(uint32_t);
-    hipLaunchKernelGGL((k_count_mfma_lds<WM, WN, true, FP4, S, WEIGHTED, PIPE, GROUPED>), dim3((unsigned)ntiles), block, lds,
+    hipLaunchKernelGGL((k_count_mfma_lds<WM, WN, true, FP4, S, WEIGHTED, PIPE, GROUPED, UNSCALED>), dim3((unsigned)ntiles), block, lds,
                        st, bits, N, W, nb, kmax, rb_stats);
   }
   return hipGetLastError();
@@ -664,7 +676,8 @@ hipError_t launch_by_variant(int v, const uint64_t* bits, int64_t N, int64_t W, 
     case 8: return launch_lds_variant<2, 4, FP4, 4, true, true>(bits, N, W, kmax, rb_stats, st);
     case 9: return launch_lds_variant<2, 2, FP4, 3, true, true>(bits, N, W, kmax, rb_stats, st);
     case 10: return launch_lds_variant<2, 4, FP4, 4, true, false, true>(bits, N, W, kmax, rb_stats, st);
-    default: return launch_lds_variant<2, 4, FP4, 4, true, true, true>(bits, N, W, kmax, rb_stats, st);
+    case 11: return launch_lds_variant<2, 4, FP4, 4, true, true, true>(bits, N, W, kmax, rb_stats, st);
+    default: return launch_lds_variant<2, 4, FP4, 4, true, false, true, true>(bits, N, W, kmax, rb_stats, st);
   }
 }
 
@@ -675,13 +688,14 @@ hipError_t launch_by_variant(int v, const uint64_t* bits, int64_t N, int64_t W, 
 // 2..5 = the LDS-staged form with 2x4 / 2x2 waves and 4 / 3 stages; 6, 7 =
 // 2x4 waves, 4 stages / 2x2 waves, 3 stages with the weighted spreading; 8,
 // 9 = the same, software-pipelined with interleaved MFMA and VALU; 10, 11 =
-// 6 and 8 with the XCD-grouped tile order.  The
-// default, 2, was the fastest on MI355X for both operand types (2D N=2^17:
-// int8 209 ms vs 224 ms for 1; fp4 136 ms vs 176 ms).  The environment
-// variable CS_MFMA_VARIANT overrides it for timing.
+// 6 and 8 with the XCD-grouped tile order; 12 = 10 with the unscaled fp4
+// MFMA encoding.  The default, 12, was the fastest on MI355X for both operand
+// types (2D N=2^17: int8 192 ms, fp4 116 ms; 10 took 192 / 120 ms, the first
+// LDS-staged form, 2, 209 / 136 ms and the register-staged form, 1, 221 /
+// 176 ms).  The environment variable CS_MFMA_VARIANT overrides it for timing.
 static int mfma_variant() {
   const char* e = getenv("CS_MFMA_VARIANT");
-  return e ? atoi(e) : 2;
+  return e ? atoi(e) : 12;
 }
 
 hipError_t launch_count_mfma(const uint64_t* bits, int64_t N, int64_t W, int kmax,
@@ -699,16 +713,16 @@ hipError_t launch_count_mfma_fp4(const uint64_t* bits, int64_t N, int64_t W, int
 
 namespace {
 template <int WM, int WN, bool FP4, int S, bool WEIGHTED = false, bool PIPE = false,
-          bool GROUPED = false>
+          bool GROUPED = false, bool UNSCALED = false>
 hipError_t set_lds_limits() {
   const int stages = S * kStageBytes;
   const int full = stages + (kLdsBins + 1) * (int)sizeof(uint32_t);
   hipError_t e = hipFuncSetAttribute(
-      (const void*)k_count_mfma_lds<WM, WN, false, FP4, S, WEIGHTED, PIPE, GROUPED>,
+      (const void*)k_count_mfma_lds<WM, WN, false, FP4, S, WEIGHTED, PIPE, GROUPED, UNSCALED>,
       hipFuncAttributeMaxDynamicSharedMemorySize, stages);
   if (e == hipSuccess)
     e = hipFuncSetAttribute(
-        (const void*)k_count_mfma_lds<WM, WN, true, FP4, S, WEIGHTED, PIPE, GROUPED>,
+        (const void*)k_count_mfma_lds<WM, WN, true, FP4, S, WEIGHTED, PIPE, GROUPED, UNSCALED>,
         hipFuncAttributeMaxDynamicSharedMemorySize, full);
   return e;
 }
@@ -738,6 +752,8 @@ hipError_t init_count_mfma() {
   if (e == hipSuccess) e = set_lds_limits<2, 4, true, 4, true, false, true>();
   if (e == hipSuccess) e = set_lds_limits<2, 4, false, 4, true, true, true>();
   if (e == hipSuccess) e = set_lds_limits<2, 4, true, 4, true, true, true>();
+  if (e == hipSuccess) e = set_lds_limits<2, 4, false, 4, true, false, true, true>();
+  if (e == hipSuccess) e = set_lds_limits<2, 4, true, 4, true, false, true, true>();
   return e;
 }
 
