@@ -450,15 +450,19 @@ __device__ __forceinline__ void mfma_tile(const uint64_t* __restrict__ bits, int
 // block BJ) travel global -> LDS by 16-byte LDS DMA loads (no registers, no
 // VALU), S chunks in flight, so the wait for memory overlaps S-1 chunks of
 // MFMA work.  A stage is 1024 slots of 16 bytes: slot 2r + s holds half
-// s ^ ((r >> 2) & 1) of stage row r (rows 0..255 = A, 256..511 = B), so the
-// 8 lanes of one ds_read_b128 pass (8 consecutive rows, one half) cover all
-// 32 banks, and two neighbouring lanes of a DMA load read the two halves of
-// one row (32 contiguous bytes).  Each row is read from global memory once
+// s ^ f(r), f(r) = bit 2 of r XOR bit 3 of r, of stage row r (rows 0..255 =
+// A, 256..511 = B).  The 16 lanes of rows r..r+15 reading one half then hit
+// 16 different 16-byte bank groups (slot mod 16 distinct: rows r and r+8
+// differ in f), and so do any 8 of them mod 8 (rows r and r+4 differ in f),
+// whether a ds_read_b128 pass serves 8 or 16 lanes; two neighbouring lanes of
+// a DMA load read the two halves of one row (32 contiguous bytes).  Each row is read from global memory once
 // per workgroup instead of once per wave that uses it.
 constexpr int kStageBytes = 512 * 32;
 
+__device__ __forceinline__ int stage_swz(int r) { return ((r >> 2) ^ (r >> 3)) & 1; }
+
 __device__ __forceinline__ uint32_t stage_slot(int r, int half) {
-  return (uint32_t)(2 * r + (half ^ ((r >> 2) & 1)));
+  return (uint32_t)(2 * r + (half ^ stage_swz(r)));
 }
 
 template <int WM, int WN, bool FULL, bool FP4, int S, bool WEIGHTED, bool PIPE = false,
@@ -492,7 +496,7 @@ __device__ __forceinline__ void mfma_tile_lds(const uint64_t* __restrict__ bits,
     const bool side_b = slot0 >= 512;
     const int slot = slot0 + lane;
     const int r = (slot >> 1) & 255;
-    const int half = (slot & 1) ^ ((r >> 2) & 1);
+    const int half = (slot & 1) ^ stage_swz(r);
     const int64_t blk = side_b ? BJ : BI;
     gbase[p] = (const char*)(bits + blk * kBT * W);
     const bool valid = blk * kBT + r < N;
@@ -614,7 +618,9 @@ __global__ __launch_bounds__(512, 1) void k_batch_count_mfma(BatchDev b) {
     unpack_item(b.mfma_items[it], &set, &BI, &BJ);
     const BatchSet bs = b.sets[set];
     if constexpr (LDS)
-      mfma_tile_lds<2, 4, false, false, 4, true, false>(b.bits + bs.bits_off, bs.N, bs.W, BI, BJ, 3,
+      // fp4 (unscaled encoding, weighted spreading): exact for the batch's
+      // N <= 16384 < 2^24, and faster than int8
+      mfma_tile_lds<2, 4, false, true, 4, true, false, true>(b.bits + bs.bits_off, bs.N, bs.W, BI, BJ, 3,
                                            b.stats + bs.stats_off, nullptr, smem);
     else
       mfma_tile<2, 4, false>(b.bits + bs.bits_off, bs.N, bs.W, BI, BJ, 3, b.stats + bs.stats_off,
