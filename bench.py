@@ -17,6 +17,7 @@ Also reported on the same line:
     the same set, on this host's cores;
   * kernels: the link kernel's HBM rate, and the popcount kernel on the same
     matrix (once) with its integer-ALU fraction;
+  * other_configs: the 2D N=1024 and 4D N=16384 single-set workloads;
   * ensemble: 512 sets (N uniform in [256, 4096], d in {2, 4}) as BD
     actions/s, batched (one cs_batch_run) vs per-set (a loop of cs_* calls);
   * desitter: ten (1+1) de Sitter slabs of 2^15 elements (eta0 = 0.5), the
@@ -249,6 +250,35 @@ def ensemble(cs, ctx, nsets=512):
     return out
 
 
+def small_configs(cs, ctx, stream, ev):
+    """The other two single-set workloads: 2D N=1024 (seed 1) and 4D N=16384
+    (seed 2).  Whole step and count call timed, 3 warm-ups, 5 timed."""
+    out = {}
+    for name, d, N, seed in (("2d_1024", 2, 1024, 1), ("4d_16384", 4, 16384, 2)):
+        steps, counts = [], []
+        for k in range(8):
+            t0 = time.perf_counter()
+            s = cs.cs_sprinkle(ctx, d, N, seed)
+            cs.cs_link(ctx, s)
+            ev[1].record(stream)
+            n, R, sm = cs.cs_interval_abundances(ctx, s, 3, 0)
+            ev[2].record(stream)
+            S = cs.cs_bd_action(ctx, s)
+            ev[2].synchronize()
+            if k >= 3:
+                steps.append((time.perf_counter() - t0) * 1e3)
+                counts.append(ev[1].elapsed_time(ev[2]))
+            path = cs.cs_set_count_path(s)
+            cs.cs_set_free(s)
+        out[name] = {"N": N, "d": d, "related_pairs": R, "abundances": [int(x) for x in n], "action": S,
+                     "count_path": {1: "pop", 2: "mfma_int8", 3: "mfma_fp4"}[path],
+                     "ms_per_step": float(np.mean(steps)), "count_ms": float(np.mean(counts)),
+                     "pairs_per_s": R / (float(np.mean(steps)) / 1e3)}
+        log("%s: step %.3f ms, count %.3f ms (%s)" % (name, out[name]["ms_per_step"], out[name]["count_ms"],
+                                                     out[name]["count_path"]))
+    return out
+
+
 def desitter(cs, ctx, N=32768, graphs=10, eta0=0.5, eps=2.0**-6):
     """The paper's de Sitter experiment (Sec. 6.1): ten (1+1) de Sitter slabs
     of N elements at eta0, the smeared action with eps, against the
@@ -412,6 +442,7 @@ def main():
         log("popcount path on the same set: %.1f ms" % (t_pop * 1000.0))
     cs.cs_set_free(s)
 
+    small = small_configs(cs, ctx, stream, ev)
     ens = None if a.no_batch else ensemble(cs, ctx)
     dsx = None if a.no_desitter else desitter(cs, ctx)
     srv = None
@@ -433,6 +464,7 @@ def main():
                    "action": S, "count_path": {1: "pop", 2: "mfma_int8", 3: "mfma_fp4"}[path_used]},
         "roofline": roof,
         "kernels": kernels,
+        "other_configs": small,
         "cpu_baseline": cpu,
         "ensemble": ens,
         "desitter": dsx,

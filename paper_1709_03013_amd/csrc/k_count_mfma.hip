@@ -174,7 +174,8 @@ template <int TM, int TN, int kThreads, bool FULL, int SHIFT, typename Acc>
 __device__ __forceinline__ void mfma_epilogue(const Acc (&acc)[TM][TN], const uint64_t* __restrict__ bits,
                                               int64_t N, int64_t W, int64_t BI, int64_t BJ,
                                               int64_t I0, int64_t J0, int kmax,
-                                              uint64_t* __restrict__ rb_stats, uint32_t* lds_hist) {
+                                              uint64_t* __restrict__ rb_stats, uint32_t* lds_hist,
+                                              const uint64_t (*pre)[TM] = nullptr) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int r32 = lane & 31, g = lane >> 5;
@@ -189,7 +190,7 @@ __device__ __forceinline__ void mfma_epilogue(const Acc (&acc)[TM][TN], const ui
 #pragma unroll
     for (int a = 0; a < TM; ++a) {
       const int64_t ibase = I0 + 32 * a;
-      const uint64_t rw = j < N ? bits[j * W + (ibase >> 6)] : 0ull;
+      const uint64_t rw = pre ? pre[b][a] : (j < N ? bits[j * W + (ibase >> 6)] : 0ull);
       uint32_t r = (uint32_t)(rw >> (ibase & 63));
       if (BI == BJ) {
         const int64_t lim = j - ibase;  // rows ri < lim have i < j
@@ -466,7 +467,7 @@ __device__ __forceinline__ uint32_t stage_slot(int r, int half) {
 }
 
 template <int WM, int WN, bool FULL, bool FP4, int S, bool WEIGHTED, bool PIPE = false,
-          bool UNSCALED = false>
+          bool UNSCALED = false, bool XPF = false>
 __device__ __forceinline__ void mfma_tile_lds(const uint64_t* __restrict__ bits, int64_t N,
                                               int64_t W, int64_t BI, int64_t BJ, int kmax,
                                               uint64_t* __restrict__ rb_stats,
@@ -530,6 +531,69 @@ __device__ __forceinline__ void mfma_tile_lds(const uint64_t* __restrict__ bits,
       for (int v = 0; v < 16; ++v) acc[a][b][v] = 0;
 
   const int64_t c0 = BI, c1 = BJ;
+  auto read_frags = [&](int stg, uint32_t (&ya)[TM][4], uint32_t (&yb)[TN][4]) {
+    const char* sb = stages + stg * kStageBytes;
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+      const uint4 v = *(const uint4*)(sb + aoff[t]);
+      ya[t][0] = v.x; ya[t][1] = v.y; ya[t][2] = v.z; ya[t][3] = v.w;
+    }
+#pragma unroll
+    for (int t = 0; t < TN; ++t) {
+      const uint4 v = *(const uint4*)(sb + boff[t]);
+      yb[t][0] = v.x; yb[t][1] = v.y; yb[t][2] = v.z; yb[t][3] = v.w;
+    }
+  };
+  auto chunk = [&](uint32_t (&ya)[TM][4], uint32_t (&yb)[TN][4], int64_t c) {
+    if constexpr (PIPE)
+      mfma_chunk_pipelined<TM, TN, FP4>(acc, ya, yb, I0, J0, c, c == c0, c == c1);
+    else
+      mfma_chunk<TM, TN, FP4, WEIGHTED, UNSCALED>(acc, ya, yb, I0, J0, c, c == c0, c == c1);
+  };
+  if constexpr (XPF) {
+    // The epilogue's relation words are loaded first (they arrive during the
+    // tile), and each chunk's operands are read from LDS one chunk ahead, so
+    // neither latency stalls the matrix core.  S stages hold chunks c..c+S-1
+    // at step c; the stage of chunk c is refilled (with chunk c+S) once every
+    // wave has read it, which the barrier of step c guarantees.
+    uint64_t pre[TN][TM];
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+#pragma unroll
+      for (int a = 0; a < TM; ++a) {
+        const int64_t j = J0 + 32 * b + r32;
+        pre[b][a] = j < N ? bits[j * W + ((I0 + 32 * a) >> 6)] : 0ull;
+      }
+#pragma unroll
+    for (int k = 0; k < S; ++k) issue(c0 + k <= c1 ? c0 + k : c1, k);
+    asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(L * (S - 1)) : "memory");
+    uint32_t xa[TM][4], xb[TN][4], na[TM][4], nb[TN][4];
+    read_frags(0, xa, xb);
+    int st = 0;
+    // One step: make chunk c+1 ready, refill chunk c's stage, read chunk
+    // c+1 into (ya, yb), contract chunk c from (xa2, xb2).  Two steps per
+    // iteration swap the register sets without copies.
+    auto step = [&](int64_t c, uint32_t (&cur_a)[TM][4], uint32_t (&cur_b)[TN][4],
+                    uint32_t (&nxt_a)[TM][4], uint32_t (&nxt_b)[TN][4]) {
+      asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(L * (S - 2)) : "memory");
+      issue(c + S <= c1 ? c + S : c1, st);
+      const int nst = st == S - 1 ? 0 : st + 1;
+      if (c < c1) read_frags(nst, nxt_a, nxt_b);
+      chunk(cur_a, cur_b, c);
+      st = nst;
+    };
+    int64_t c = c0;
+    for (; c + 1 <= c1; c += 2) {
+      step(c, xa, xb, na, nb);
+      step(c + 1, na, nb, xa, xb);
+    }
+    if (c <= c1) step(c, xa, xb, na, nb);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    mfma_epilogue<TM, TN, kThreads, FULL, ((WEIGHTED || PIPE) && !FP4) ? 6 : 0>(
+        acc, bits, N, W, BI, BJ, I0, J0, kmax, rb_stats, lds_hist, pre);
+    return;
+  }
+  // (c0, c1 as above)
   // Prologue: chunks c0 .. c0+S-2 (clamped to c1: a clamped load refills a
   // stage nobody reads again, so every wave always has the same number of
   // loads in flight and the wait count below is a constant).
@@ -570,7 +634,7 @@ __device__ __forceinline__ void mfma_tile_lds(const uint64_t* __restrict__ bits,
 }
 
 template <int WM, int WN, bool FULL, bool FP4, int S, bool WEIGHTED, bool PIPE, bool GROUPED,
-          bool UNSCALED>
+          bool UNSCALED, bool XPF>
 __global__ __launch_bounds__(64 * WM * WN, 1) void k_count_mfma_lds(
     const uint64_t* __restrict__ bits, int64_t N, int64_t W, int64_t nb,
     int kmax, uint64_t* __restrict__ rb_stats) {
@@ -587,8 +651,8 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void k_count_mfma_lds(
     for (int b = threadIdx.x; b <= lb; b += 64 * WM * WN) lds_hist[b] = 0;
     __syncthreads();
   }
-  mfma_tile_lds<WM, WN, FULL, FP4, S, WEIGHTED, PIPE, UNSCALED>(bits, N, W, BI, BJ, kmax, rb_stats,
-                                                                lds_hist, smem);
+  mfma_tile_lds<WM, WN, FULL, FP4, S, WEIGHTED, PIPE, UNSCALED, XPF>(bits, N, W, BI, BJ, kmax,
+                                                                     rb_stats, lds_hist, smem);
 }
 
 template <int WM, int WN, bool FULL, bool FP4>
@@ -647,7 +711,7 @@ hipError_t launch_variant(const uint64_t* bits, int64_t N, int64_t W, int kmax,
 }
 
 template <int WM, int WN, bool FP4, int S, bool WEIGHTED = false, bool PIPE = false,
-          bool GROUPED = false, bool UNSCALED = false>
+          bool GROUPED = false, bool UNSCALED = false, bool XPF = false>
 hipError_t launch_lds_variant(const uint64_t* bits, int64_t N, int64_t W, int kmax,
                               uint64_t* rb_stats, hipStream_t st) {
   const int64_t nb = (N + kBT - 1) / kBT;
@@ -656,12 +720,12 @@ hipError_t launch_lds_variant(const uint64_t* bits, int64_t N, int64_t W, int km
   const dim3 block(64 * WM * WN);
   const size_t stage_bytes = (size_t)S * kStageBytes;
   if (kmax <= 3) {
-    hipLaunchKernelGGL((k_count_mfma_lds<WM, WN, false, FP4, S, WEIGHTED, PIPE, GROUPED, UNSCALED>), dim3((unsigned)ntiles), block,
+    hipLaunchKernelGGL((k_count_mfma_lds<WM, WN, false, FP4, S, WEIGHTED, PIPE, GROUPED, UNSCALED, XPF>), dim3((unsigned)ntiles), block,
                        stage_bytes, st, bits, N, W, nb, kmax, rb_stats);
   } else {
     const size_t lds = stage_bytes +
                        (size_t)((kmax + 1 < kLdsBins ? kmax + 1 : kLdsBins) + 1) * sizeof(uint32_t);
-    hipLaunchKernelGGL((k_count_mfma_lds<WM, WN, true, FP4, S, WEIGHTED, PIPE, GROUPED, UNSCALED>), dim3((unsigned)ntiles), block, lds,
+    hipLaunchKernelGGL((k_count_mfma_lds<WM, WN, true, FP4, S, WEIGHTED, PIPE, GROUPED, UNSCALED, XPF>), dim3((unsigned)ntiles), block, lds,
                        st, bits, N, W, nb, kmax, rb_stats);
   }
   return hipGetLastError();
@@ -683,7 +747,8 @@ hipError_t launch_by_variant(int v, const uint64_t* bits, int64_t N, int64_t W, 
     case 9: return launch_lds_variant<2, 2, FP4, 3, true, true>(bits, N, W, kmax, rb_stats, st);
     case 10: return launch_lds_variant<2, 4, FP4, 4, true, false, true>(bits, N, W, kmax, rb_stats, st);
     case 11: return launch_lds_variant<2, 4, FP4, 4, true, true, true>(bits, N, W, kmax, rb_stats, st);
-    default: return launch_lds_variant<2, 4, FP4, 4, true, false, true, true>(bits, N, W, kmax, rb_stats, st);
+    case 12: return launch_lds_variant<2, 4, FP4, 4, true, false, true, true>(bits, N, W, kmax, rb_stats, st);
+    default: return launch_lds_variant<2, 4, FP4, 4, true, false, true, true, true>(bits, N, W, kmax, rb_stats, st);
   }
 }
 
@@ -695,10 +760,13 @@ hipError_t launch_by_variant(int v, const uint64_t* bits, int64_t N, int64_t W, 
 // 2x4 waves, 4 stages / 2x2 waves, 3 stages with the weighted spreading; 8,
 // 9 = the same, software-pipelined with interleaved MFMA and VALU; 10, 11 =
 // 6 and 8 with the XCD-grouped tile order; 12 = 10 with the unscaled fp4
-// MFMA encoding.  The default, 12, was the fastest on MI355X for both operand
-// types (2D N=2^17: int8 192 ms, fp4 116 ms; 10 took 192 / 120 ms, the first
-// LDS-staged form, 2, 209 / 136 ms and the register-staged form, 1, 221 /
-// 176 ms).  The environment variable CS_MFMA_VARIANT overrides it for timing.
+// MFMA encoding; 13 = 12 reading each chunk's operands from LDS one chunk
+// ahead and the epilogue's relation words at the start of the tile (no
+// faster: LDS latency is not what limits the kernel).  The default, 12, was
+// the fastest on MI355X for both operand types (2D N=2^17: int8 186 ms, fp4
+// 110-112 ms; the first LDS-staged form, 2, took 209 / 136 ms and the
+// register-staged form, 1, 221 / 176 ms).  The environment variable
+// CS_MFMA_VARIANT overrides it for timing.
 static int mfma_variant() {
   const char* e = getenv("CS_MFMA_VARIANT");
   return e ? atoi(e) : 12;
@@ -719,16 +787,16 @@ hipError_t launch_count_mfma_fp4(const uint64_t* bits, int64_t N, int64_t W, int
 
 namespace {
 template <int WM, int WN, bool FP4, int S, bool WEIGHTED = false, bool PIPE = false,
-          bool GROUPED = false, bool UNSCALED = false>
+          bool GROUPED = false, bool UNSCALED = false, bool XPF = false>
 hipError_t set_lds_limits() {
   const int stages = S * kStageBytes;
   const int full = stages + (kLdsBins + 1) * (int)sizeof(uint32_t);
   hipError_t e = hipFuncSetAttribute(
-      (const void*)k_count_mfma_lds<WM, WN, false, FP4, S, WEIGHTED, PIPE, GROUPED, UNSCALED>,
+      (const void*)k_count_mfma_lds<WM, WN, false, FP4, S, WEIGHTED, PIPE, GROUPED, UNSCALED, XPF>,
       hipFuncAttributeMaxDynamicSharedMemorySize, stages);
   if (e == hipSuccess)
     e = hipFuncSetAttribute(
-        (const void*)k_count_mfma_lds<WM, WN, true, FP4, S, WEIGHTED, PIPE, GROUPED, UNSCALED>,
+        (const void*)k_count_mfma_lds<WM, WN, true, FP4, S, WEIGHTED, PIPE, GROUPED, UNSCALED, XPF>,
         hipFuncAttributeMaxDynamicSharedMemorySize, full);
   return e;
 }
@@ -760,6 +828,8 @@ hipError_t init_count_mfma() {
   if (e == hipSuccess) e = set_lds_limits<2, 4, true, 4, true, true, true>();
   if (e == hipSuccess) e = set_lds_limits<2, 4, false, 4, true, false, true, true>();
   if (e == hipSuccess) e = set_lds_limits<2, 4, true, 4, true, false, true, true>();
+  if (e == hipSuccess) e = set_lds_limits<2, 4, false, 4, true, false, true, true, true>();
+  if (e == hipSuccess) e = set_lds_limits<2, 4, true, 4, true, false, true, true, true>();
   return e;
 }
 

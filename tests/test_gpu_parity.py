@@ -60,6 +60,7 @@ def test_sprinkle_and_link_match_oracle(cs, ctx, d, N, seed):
     say("case sprinkle+link d=%d N=%d seed=%d" % (d, N, seed))
     s = gpu_set(cs, ctx, d, N, seed)
     try:
+        assert cs.cs_set_manifold(s) == (cs.CS_MANIFOLD_DIAMOND, d)
         coords, orig = cs.cs_get_coords(ctx, s)
         oc, oo, _ = oracle.sprinkle(d, N, seed)
         assert np.array_equal(coords.view(np.uint64), oc.view(np.uint64))
