@@ -228,13 +228,16 @@ typedef struct {
 } cs_result;
 
 #define CS_BATCH_NMAX 16384
-/* Run a whole ensemble: every set is sprinkled, sorted, linked, counted and
- * its action evaluated, with all sets sharing each launch (one persistent
- * counting launch pulling (set, tile) work items from a device queue).  The
- * launch sequence is captured once per batch shape in a hipGraph and
- * replayed.  out[s] is the result of reqs[s]; identical to running the set
- * alone.  Device memory comes from the context's pool (CS_ENOMEM if the
- * batch does not fit the budget). */
+/* Run a whole ensemble (the Monte Carlo use of Sec. 1.2): every set is
+ * sprinkled, sorted, linked, counted and its action evaluated, with all sets
+ * sharing each launch (the counting is one persistent launch over the (set,
+ * tile) work items of every set, sorted longest first and dealt to a fixed
+ * grid in snake order; sets of 64 or more elements use the fp4 matrix-core
+ * count).  The launch sequence is captured once per batch shape in a hipGraph
+ * and replayed.  out[s] is the result of reqs[s]; identical to running the
+ * set alone.  A request with d not 2 or 4 or N outside [0, CS_BATCH_NMAX]
+ * gets status CS_EINVAL in its own result.  Device memory comes from the
+ * context's pool (CS_ENOMEM if the batch does not fit the budget). */
 cs_status cs_batch_run(cs_ctx* ctx, int nsets, const cs_req* reqs,
                        cs_result* out);
 
