@@ -60,9 +60,9 @@ PEAK = {
 # any change to them the figure no longer describes the kernel and is
 # reported as null.
 TRAFFIC = {
-    # FETCH_SIZE 51469611 KiB x 2 (the counter reads 0.5 KiB per KiB of a plain
-    # copy) + WRITE_SIZE 93312 KiB x 1, per launch on this workload
-    "k_count_mfma_lds<fp4>": {"sources": "7d88ef41f368bcf4", "bytes": 105502416795},
+    # FETCH_SIZE 50336831 KiB / 0.5 (the counter reads 0.5 KiB per KiB of a
+    # plain copy) + WRITE_SIZE 93312 KiB / 1.0, per launch on this workload
+    "k_count_mfma_lds<fp4>": {"sources": "2a4de5643d649a8d", "bytes": 103182546122},
 }
 KERNEL_SOURCES = {
     "k_count_mfma_lds<int8>": ["k_count_mfma.hip", "cs_device.h", "cs_internal.h"],
