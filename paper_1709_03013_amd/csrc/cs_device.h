@@ -41,29 +41,6 @@ __device__ __forceinline__ bool tile_xcd_grouped(int64_t id, int64_t nb, int64_t
   return *bi <= *bj && *bj < nb;
 }
 
-// The same order for half tiles (256 rows x 128 columns): the 128 halves of
-// super-tile g get ids congruent to g mod 8; h selects the column half.
-// Halves that start at or past N are padding too.
-__device__ __forceinline__ bool half_tile_xcd_grouped(int64_t id, int64_t nb, int64_t N,
-                                                      int64_t* bi, int64_t* bj, int64_t* h) {
-  const int64_t nbs = (nb + 7) / 8;
-  const int64_t x = id & 7, r = id >> 10, t = (id >> 3) & 127;
-  const int64_t g = 8 * r + x;
-  if (g >= nbs * (nbs + 1) / 2) return false;
-  int64_t sa, sb;
-  tri_tile_longest_first(g, nbs, &sa, &sb);
-  *bi = 8 * sa + (t >> 4);
-  *bj = 8 * sb + ((t >> 1) & 7);
-  *h = t & 1;
-  return *bi <= *bj && *bj < nb && *bj * 256 + *h * 128 < N;
-}
-
-__host__ __device__ inline int64_t half_grouped_ids(int64_t nb) {
-  const int64_t nbs = (nb + 7) / 8;
-  const int64_t ns = nbs * (nbs + 1) / 2;
-  return (ns + 7) / 8 * 1024;
-}
-
 // Number of workgroup ids tile_xcd_grouped needs for nb blocks.
 __host__ __device__ inline int64_t xcd_grouped_ids(int64_t nb) {
   const int64_t nbs = (nb + 7) / 8;

@@ -633,255 +633,6 @@ __device__ __forceinline__ void mfma_tile_lds(const uint64_t* __restrict__ bits,
                                                                    kmax, rb_stats, lds_hist);
 }
 
-// ---- LDS-staged half tiles --------------------------------------------------
-// A workgroup of 4 waves (2x2, each 128x64 pairs) takes half a tile: 256 rows
-// x 128 columns; two workgroups share a CU.  Each has its own barriers, so
-// the two waves on a SIMD are no longer held in step by one workgroup-wide
-// barrier per chunk.  Stage: 384 rows (256 A, 128 B) x 32 bytes, same
-// swizzle, 3 DMA loads per wave per chunk.  Weighted spreading, unscaled fp4.
-constexpr int kHalfStageBytes = 384 * 32;
-
-template <bool FULL, bool FP4, int S>
-__device__ __forceinline__ void mfma_tile_half(const uint64_t* __restrict__ bits, int64_t N,
-                                               int64_t W, int64_t BI, int64_t BJ, int64_t H,
-                                               int kmax, uint64_t* __restrict__ rb_stats,
-                                               uint32_t* lds_hist, char* stages) {
-  constexpr int WM = 2, WN = 2, kThreads = 256;
-  constexpr int TM = 4, TN = 2;
-  constexpr int L = 768 / kThreads;  // 3
-  static_assert(S >= 2 && L * (S - 2) <= 63, "bad stage shape");
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int r32 = lane & 31, g = lane >> 5;
-  const int64_t I0 = BI * kBT + (wave / WN) * (32 * TM);
-  const int64_t Jb = BJ * kBT + H * 128;  // first column of the half tile
-  const int64_t J0 = Jb + (wave % WN) * (32 * TN);
-
-  const char* gbase[L];
-  uint32_t goff[L];
-#pragma unroll
-  for (int p = 0; p < L; ++p) {
-    const int slot0 = (wave * L + p) * 64;  // uniform
-    const bool side_b = slot0 >= 512;
-    const int slot = slot0 + lane;
-    const int r = (slot >> 1) & 255;
-    const int half = (slot & 1) ^ stage_swz(r);
-    const int64_t base = side_b ? Jb : BI * kBT;
-    gbase[p] = (const char*)(bits + base * W);
-    const bool valid = base + r < N;
-    goff[p] = (uint32_t)((valid ? (int64_t)r * W * 8 : 0) + 16 * half);
-  }
-  typedef __attribute__((address_space(3))) void* lds_ptr;
-  typedef __attribute__((address_space(1))) const void* global_ptr;
-  auto issue = [&](int64_t c, int st) {
-#pragma unroll
-    for (int p = 0; p < L; ++p)
-      __builtin_amdgcn_global_load_lds((global_ptr)(gbase[p] + c * 32 + goff[p]),
-                                       (lds_ptr)(stages + st * kHalfStageBytes + (wave * L + p) * 1024),
-                                       16, 0, 0);
-  };
-  uint32_t aoff[TM], boff[TN];
-#pragma unroll
-  for (int t = 0; t < TM; ++t)
-    aoff[t] = 16u * stage_slot((wave / WN) * (32 * TM) + 32 * t + r32, g);
-#pragma unroll
-  for (int t = 0; t < TN; ++t)
-    boff[t] = 16u * stage_slot(256 + (wave % WN) * (32 * TN) + 32 * t + r32, g);
-
-  using Acc = typename std::conditional<FP4, v16f, v16i>::type;
-  Acc acc[TM][TN];
-#pragma unroll
-  for (int a = 0; a < TM; ++a)
-#pragma unroll
-    for (int b = 0; b < TN; ++b)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[a][b][v] = 0;
-
-  const int64_t c0 = BI, c1 = BJ;
-#pragma unroll
-  for (int k = 0; k < S - 1; ++k) issue(c0 + k <= c1 ? c0 + k : c1, k);
-  int st = 0;
-  for (int64_t c = c0; c <= c1; ++c) {
-    asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(L * (S - 2)) : "memory");
-    issue(c + S - 1 <= c1 ? c + S - 1 : c1, st == 0 ? S - 1 : st - 1);
-    const char* sb = stages + st * kHalfStageBytes;
-    uint32_t xa[TM][4], xb[TN][4];
-#pragma unroll
-    for (int t = 0; t < TM; ++t) {
-      const uint4 v = *(const uint4*)(sb + aoff[t]);
-      xa[t][0] = v.x; xa[t][1] = v.y; xa[t][2] = v.z; xa[t][3] = v.w;
-    }
-#pragma unroll
-    for (int t = 0; t < TN; ++t) {
-      const uint4 v = *(const uint4*)(sb + boff[t]);
-      xb[t][0] = v.x; xb[t][1] = v.y; xb[t][2] = v.z; xb[t][3] = v.w;
-    }
-    mfma_chunk<TM, TN, FP4, true, true>(acc, xa, xb, I0, J0, c, c == c0, c == c1);
-    st = st == S - 1 ? 0 : st + 1;
-  }
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  mfma_epilogue<TM, TN, kThreads, FULL, FP4 ? 0 : 6>(acc, bits, N, W, BI, BJ, I0, J0, kmax, rb_stats,
-                                                     lds_hist);
-}
-
-template <bool FULL, bool FP4, int S>
-__global__ __launch_bounds__(256, 2) void k_count_mfma_half(const uint64_t* __restrict__ bits,
-                                                            int64_t N, int64_t W, int64_t nb,
-                                                            int kmax, uint64_t* __restrict__ rb_stats) {
-  extern __shared__ __align__(16) char smem[];  // S stages, then (FULL) lb+1 bins
-  uint32_t* lds_hist = (uint32_t*)(smem + S * kHalfStageBytes);
-  int64_t BI, BJ, H;
-  if (!half_tile_xcd_grouped((int64_t)blockIdx.x, nb, N, &BI, &BJ, &H)) return;  // whole workgroup
-  if constexpr (FULL) {
-    const int lb = kmax + 1 < kLdsBins ? kmax + 1 : kLdsBins;
-    for (int b = threadIdx.x; b <= lb; b += 256) lds_hist[b] = 0;
-    __syncthreads();
-  }
-  mfma_tile_half<FULL, FP4, S>(bits, N, W, BI, BJ, H, kmax, rb_stats, lds_hist, smem);
-}
-
-// ---- LDS-staged form with shared A spreading ------------------------------
-// In the 2x4 layout each 32-row A fragment feeds the 4 waves of its wave row,
-// and each of them spread it on its own: 4/5 of the VALU work of a chunk.
-// Here wave w spreads A fragment w (rows 32w..32w+31 of the row block) once
-// per chunk, fp4 weighted form, into an LDS buffer (4 steps x 8 fragments x
-// 64 lanes x 16 bytes = 32 KiB), and every wave reads its 4 A operands from
-// there; B fragments (2 per wave, shared by 2 waves) are still spread by each
-// wave.  Two barriers per chunk: one for the DMA'd chunk, one for the spread
-// operands.  fp4 only, counts up to kmax = 3 (the full histogram uses the
-// form above).
-constexpr int kSpreadBytes = 4 * 8 * 64 * 16;
-
-template <int S>
-__device__ __forceinline__ void mfma_tile_shared(const uint64_t* __restrict__ bits, int64_t N,
-                                                 int64_t W, int64_t BI, int64_t BJ,
-                                                 uint64_t* __restrict__ rb_stats, char* stages,
-                                                 char* spread) {
-  constexpr int WM = 2, WN = 4, kWaves = 8, kThreads = 512;
-  constexpr int TM = 4, TN = 2;
-  constexpr int L = 1024 / kThreads;
-  static_assert(S >= 2 && L * (S - 2) <= 63, "bad stage shape");
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int r32 = lane & 31, g = lane >> 5;
-  const int64_t I0 = BI * kBT + (wave / WN) * (32 * TM);
-  const int64_t J0 = BJ * kBT + (wave % WN) * (32 * TN);
-  const int64_t IW = BI * kBT + 32 * wave;  // first row of the A fragment this wave spreads
-
-  const char* gbase[L];
-  uint32_t goff[L];
-#pragma unroll
-  for (int p = 0; p < L; ++p) {
-    const int slot0 = (wave * L + p) * 64;
-    const bool side_b = slot0 >= 512;
-    const int slot = slot0 + lane;
-    const int r = (slot >> 1) & 255;
-    const int half = (slot & 1) ^ stage_swz(r);
-    const int64_t blk = side_b ? BJ : BI;
-    gbase[p] = (const char*)(bits + blk * kBT * W);
-    const bool valid = blk * kBT + r < N;
-    goff[p] = (uint32_t)((valid ? (int64_t)r * W * 8 : 0) + 16 * half);
-  }
-  typedef __attribute__((address_space(3))) void* lds_ptr;
-  typedef __attribute__((address_space(1))) const void* global_ptr;
-  auto issue = [&](int64_t c, int st) {
-#pragma unroll
-    for (int p = 0; p < L; ++p)
-      __builtin_amdgcn_global_load_lds((global_ptr)(gbase[p] + c * 32 + goff[p]),
-                                       (lds_ptr)(stages + st * kStageBytes + (wave * L + p) * 1024),
-                                       16, 0, 0);
-  };
-  const uint32_t woff = 16u * stage_slot(32 * wave + r32, g);  // the fragment this wave spreads
-  uint32_t boff[TN];
-#pragma unroll
-  for (int t = 0; t < TN; ++t)
-    boff[t] = 16u * stage_slot(256 + (wave % WN) * (32 * TN) + 32 * t + r32, g);
-  // spread[q][F][lane]: 16 bytes each
-  auto sp_addr = [&](int q, int F) { return spread + ((q * 8 + F) * 64 + lane) * 16; };
-
-  v16f acc[TM][TN];
-#pragma unroll
-  for (int a = 0; a < TM; ++a)
-#pragma unroll
-    for (int b = 0; b < TN; ++b)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.f;
-
-  const int64_t c0 = BI, c1 = BJ;
-#pragma unroll
-  for (int k = 0; k < S - 1; ++k) issue(c0 + k <= c1 ? c0 + k : c1, k);
-  int st = 0;
-  for (int64_t c = c0; c <= c1; ++c) {
-    // chunk c in LDS; every wave finished the previous chunk's reads of the
-    // stage refilled next and of the spread buffer
-    asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(L * (S - 2)) : "memory");
-    issue(c + S - 1 <= c1 ? c + S - 1 : c1, st == 0 ? S - 1 : st - 1);
-    const char* sb = stages + st * kStageBytes;
-    {
-      const uint4 v = *(const uint4*)(sb + woff);
-      uint32_t x[4] = {v.x, v.y, v.z, v.w};
-      if (c == c0) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          x[q] &= (uint32_t)(mask_above(IW + r32, 4 * c + 2 * g + (q >> 1)) >> (32 * (q & 1)));
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const v8i f = spread_fp4_wa(x[q]);
-        uint4 o;
-        o.x = (uint32_t)f[0]; o.y = (uint32_t)f[1]; o.z = (uint32_t)f[2]; o.w = (uint32_t)f[3];
-        *(uint4*)sp_addr(q, wave) = o;
-      }
-    }
-    uint32_t xb[TN][4];
-#pragma unroll
-    for (int t = 0; t < TN; ++t) {
-      const uint4 v = *(const uint4*)(sb + boff[t]);
-      xb[t][0] = v.x; xb[t][1] = v.y; xb[t][2] = v.z; xb[t][3] = v.w;
-    }
-    if (c == c1) {
-#pragma unroll
-      for (int t = 0; t < TN; ++t)
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          xb[t][q] &= (uint32_t)(mask_below(J0 + 32 * t + r32, 4 * c + 2 * g + (q >> 1)) >> (32 * (q & 1)));
-    }
-    // the spread A operands of every wave are in LDS
-    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      v8i fa[TM], fb[TN];
-#pragma unroll
-      for (int t = 0; t < TM; ++t) {
-        const uint4 v = *(const uint4*)sp_addr(q, (wave / WN) * TM + t);
-        fa[t][0] = (int)v.x; fa[t][1] = (int)v.y; fa[t][2] = (int)v.z; fa[t][3] = (int)v.w;
-        fa[t][4] = 0; fa[t][5] = 0; fa[t][6] = 0; fa[t][7] = 0;
-      }
-#pragma unroll
-      for (int t = 0; t < TN; ++t) fb[t] = spread_fp4_wb(xb[t][q]);
-#pragma unroll
-      for (int a = 0; a < TM; ++a)
-#pragma unroll
-        for (int b = 0; b < TN; ++b) acc[a][b] = mma_fp4<true>(fa[a], fb[b], acc[a][b]);
-    }
-    st = st == S - 1 ? 0 : st + 1;
-  }
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  mfma_epilogue<TM, TN, kThreads, false, 0>(acc, bits, N, W, BI, BJ, I0, J0, 3, rb_stats, nullptr);
-}
-
-template <int S>
-__global__ __launch_bounds__(512, 1) void k_count_mfma_shared(const uint64_t* __restrict__ bits,
-                                                              int64_t N, int64_t W, int64_t nb,
-                                                              uint64_t* __restrict__ rb_stats) {
-  extern __shared__ __align__(16) char smem[];  // S stages, then the spread A operands
-  int64_t BI, BJ;
-  if (!tile_xcd_grouped((int64_t)blockIdx.x, nb, &BI, &BJ)) return;  // whole workgroup
-  mfma_tile_shared<S>(bits, N, W, BI, BJ, rb_stats, smem, smem + S * kStageBytes);
-}
-
 template <int WM, int WN, bool FULL, bool FP4, int S, bool WEIGHTED, bool PIPE, bool GROUPED,
           bool UNSCALED, bool XPF>
 __global__ __launch_bounds__(64 * WM * WN, 1) void k_count_mfma_lds(
@@ -980,45 +731,9 @@ hipError_t launch_lds_variant(const uint64_t* bits, int64_t N, int64_t W, int km
   return hipGetLastError();
 }
 
-template <int S>
-hipError_t launch_shared(const uint64_t* bits, int64_t N, int64_t W, uint64_t* rb_stats,
-                         hipStream_t st) {
-  const int64_t nb = (N + kBT - 1) / kBT;
-  const int64_t ids = xcd_grouped_ids(nb);
-  if (ids > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_count_mfma_shared<S>), dim3((unsigned)ids), dim3(512),
-                     (size_t)S * kStageBytes + kSpreadBytes, st, bits, N, W, nb, rb_stats);
-  return hipGetLastError();
-}
-
-template <bool FP4, int S>
-hipError_t launch_half(const uint64_t* bits, int64_t N, int64_t W, int kmax, uint64_t* rb_stats,
-                       hipStream_t st) {
-  const int64_t nb = (N + kBT - 1) / kBT;
-  const int64_t ids = half_grouped_ids(nb);
-  if (ids > 0x7fffffffLL) return hipErrorInvalidValue;
-  const size_t stage_bytes = (size_t)S * kHalfStageBytes;
-  if (kmax <= 3) {
-    hipLaunchKernelGGL((k_count_mfma_half<false, FP4, S>), dim3((unsigned)ids), dim3(256), stage_bytes, st,
-                       bits, N, W, nb, kmax, rb_stats);
-  } else {
-    const size_t lds = stage_bytes +
-                       (size_t)((kmax + 1 < kLdsBins ? kmax + 1 : kLdsBins) + 1) * sizeof(uint32_t);
-    hipLaunchKernelGGL((k_count_mfma_half<true, FP4, S>), dim3((unsigned)ids), dim3(256), lds, st, bits,
-                       N, W, nb, kmax, rb_stats);
-  }
-  return hipGetLastError();
-}
-
 template <bool FP4>
 hipError_t launch_by_variant(int v, const uint64_t* bits, int64_t N, int64_t W, int kmax,
                              uint64_t* rb_stats, hipStream_t st) {
-  if (v == 15) return launch_half<FP4, 4>(bits, N, W, kmax, rb_stats, st);
-  if (v == 16) return launch_half<FP4, 3>(bits, N, W, kmax, rb_stats, st);
-  if (v == 14) {
-    if (FP4 && kmax <= 3) return launch_shared<4>(bits, N, W, rb_stats, st);
-    v = 12;  // int8 and the full histogram: the unshared form
-  }
   switch (v) {
     case 0: return launch_variant<2, 2, FP4>(bits, N, W, kmax, rb_stats, st);
     case 1: return launch_variant<2, 4, FP4>(bits, N, W, kmax, rb_stats, st);
@@ -1047,10 +762,7 @@ hipError_t launch_by_variant(int v, const uint64_t* bits, int64_t N, int64_t W, 
 // 6 and 8 with the XCD-grouped tile order; 12 = 10 with the unscaled fp4
 // MFMA encoding; 13 = 12 reading each chunk's operands from LDS one chunk
 // ahead and the epilogue's relation words at the start of the tile (no
-// faster: LDS latency is not what limits the kernel); 14 = 12 with each A
-// fragment spread once per workgroup into LDS (fp4, kmax = 3; otherwise 12;
-// slower: 132 vs 111 ms); 15, 16 = half tiles, two 4-wave workgroups per CU,
-// 4 / 3 stages.
+// faster: LDS latency is not what limits the kernel).
 // The default, 12, was
 // the fastest on MI355X for both operand types (2D N=2^17: int8 186 ms, fp4
 // 110-112 ms; the first LDS-staged form, 2, took 209 / 136 ms and the
@@ -1119,22 +831,6 @@ hipError_t init_count_mfma() {
   if (e == hipSuccess) e = set_lds_limits<2, 4, true, 4, true, false, true, true>();
   if (e == hipSuccess) e = set_lds_limits<2, 4, false, 4, true, false, true, true, true>();
   if (e == hipSuccess) e = set_lds_limits<2, 4, true, 4, true, false, true, true, true>();
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_count_mfma_shared<4>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 4 * kStageBytes + kSpreadBytes);
-  const int hist = (kLdsBins + 1) * (int)sizeof(uint32_t);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_count_mfma_half<true, true, 4>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 4 * kHalfStageBytes + hist);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_count_mfma_half<true, false, 4>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 4 * kHalfStageBytes + hist);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_count_mfma_half<true, true, 3>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 3 * kHalfStageBytes + hist);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_count_mfma_half<true, false, 3>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 3 * kHalfStageBytes + hist);
   return e;
 }
 
