@@ -62,7 +62,7 @@ PEAK = {
 TRAFFIC = {
     # FETCH_SIZE 50336831 KiB / 0.5 (the counter reads 0.5 KiB per KiB of a
     # plain copy) + WRITE_SIZE 93312 KiB / 1.0, per launch on this workload
-    "k_count_mfma_lds<fp4>": {"sources": "2a4de5643d649a8d", "bytes": 103182546122},
+    "k_count_mfma_lds<fp4>": {"sources": "8d1aa427ba1529dd", "bytes": 103491937588},
 }
 KERNEL_SOURCES = {
     "k_count_mfma_lds<int8>": ["k_count_mfma.hip", "cs_device.h", "cs_internal.h"],

@@ -82,7 +82,9 @@ __device__ __forceinline__ uint64_t link_word(const double (*rowc)[64], const Pt
     const uint64_t rel = related_mask<D, DIR>(pi, pk);
     const uint64_t m = PARTIAL ? (kmask & rel) : rel;
     const int mlo = (int)(uint32_t)m, mhi = (int)(uint32_t)(m >> 32);
-    // the lane select goes through M0 (one SGPR operand per VOP3 on gfx9)
+    // the lane select goes through M0 (one SGPR operand per VOP3 on gfx9);
+    // hipcc warns that M0 is reserved: the link kernels' own code keeps no
+    // value in M0 (their only M0 writes are these statements)
     asm("s_mov_b32 m0, %4\n\tv_writelane_b32 %0, %2, m0\n\tv_writelane_b32 %1, %3, m0"
         : "+v"(lo), "+v"(hi)
         : "s"(mlo), "s"(mhi), "s"(r)
