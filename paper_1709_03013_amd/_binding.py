@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcs_gfx950.so")
 
 CS_OK, CS_EINVAL, CS_ENOMEM, CS_EDEVICE, CS_EBUSY, CS_EUNSUPPORTED = range(6)
-PATH_AUTO, PATH_POP, PATH_MFMA, PATH_MFMA_FP4 = 0, 1, 2, 3
+PATH_AUTO, PATH_POP, PATH_MFMA, PATH_MFMA_FP4, PATH_LOCAL = 0, 1, 2, 3, 4
 ROW_BLOCK = 256
 KMAX_MAX = 16777213
 STATUS_NAMES = {0: "CS_OK", 1: "CS_EINVAL", 2: "CS_ENOMEM", 3: "CS_EDEVICE",
@@ -77,6 +77,10 @@ _SIGS = {
     "cs_count_workspace_bytes": (ctypes.c_uint64, [ctypes.c_int64, ctypes.c_int]),
     "cs_count_dev": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, _vp, _vp,
                                     ctypes.c_int, _vp]),
+    "cs_local_abundances": (ctypes.c_int, [_vp, _vp, _u64p, _u64p]),
+    "cs_count_local_workspace_bytes": (ctypes.c_uint64, [ctypes.c_int64]),
+    "cs_count_local_dev": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int64, _vp, _vp,
+                                          ctypes.c_uint64, _vp]),
     "cs_batch_run": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(cs_req), ctypes.POINTER(cs_result)]),
     "cs_queue_start": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_uint64]),
     "cs_queue_submit": (ctypes.c_int, [_vp, ctypes.POINTER(cs_req), _u64p]),
@@ -248,6 +252,29 @@ def cs_interval_abundances_rows(ctx: int, s: int, kmax: int = 3, path: int = PAT
     blocks = np.zeros((nrb, kmax + 3), dtype=np.uint64)
     _check(lib().cs_interval_abundances_rows(ctx, s, kmax, _ptr(blocks, _u64p), path))
     return blocks
+
+
+def cs_local_abundances(ctx: int, s: int, blocks: bool = False):
+    """(N_0..N_3 as uint64[4], R, pairs queued) by the saturating count; with
+    blocks=True also the per-64-label-block breakdown, uint64[ceil(N/64), 5]."""
+    out = np.zeros(6, dtype=np.uint64)
+    blk = None
+    if blocks:
+        _, N, _, _ = cs_set_info(s)
+        blk = np.zeros((max((N + 63) // 64, 1), 5), dtype=np.uint64)
+    _check(lib().cs_local_abundances(ctx, s, _ptr(out, _u64p), _ptr(blk, _u64p) if blocks else None))
+    res = (out[:4].copy(), int(out[4]), int(out[5]))
+    return res + (blk,) if blocks else res
+
+
+def cs_count_local_workspace_bytes(N: int) -> int:
+    return int(lib().cs_count_local_workspace_bytes(N))
+
+
+def cs_count_local_dev(bits_dev: int, N: int, stride_words: int, stats_dev: int, work_dev: int,
+                       work_bytes: int, hip_stream: int | None):
+    _check(lib().cs_count_local_dev(bits_dev, N, stride_words, stats_dev, work_dev, work_bytes,
+                                    hip_stream))
 
 
 def cs_bd_action(ctx: int, s: int) -> float:

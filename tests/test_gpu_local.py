@@ -1,0 +1,237 @@
+"""GPU parity of the saturating count (local abundances N_0..N_3 and R) with
+the oracle's full count (Sec. 4.1 definition), called through the C ABI.
+
+Bit-exact: N_0..N_3, R, the per-block breakdown and the BD action (one
+rounding of the same exact integer bracket).  Cases cover tiles counted by
+the dense pass alone, pairs finished in the staged window, queued pairs,
+a queue too small for its pairs (the dense pass then finishes them), every
+chunk/margin setting at its limits, imported orders with very long links,
+and the full-size 2D workload against the stored oracle result."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import causet_inputs as ci
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden", "oracle_reference.json")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cs():
+    import paper_1709_03013_amd as p
+    return p
+
+
+@pytest.fixture(scope="module")
+def ctx(cs):
+    c = cs.cs_create(0, 0, None)
+    yield c
+    cs.cs_destroy(c)
+
+
+def expect(bits, N, rows=None):
+    if N <= 1:
+        return [0, 0, 0, 0], 0
+    h, R, _ = oracle.count_bits(bits, N, nbins=4, rows=rows)
+    return [int(x) for x in h], R
+
+
+def oracle_bits(d, N, seed):
+    """The oracle's own matrix of the set cs_sprinkle(d, N, seed) builds."""
+    if N <= 1:
+        return None
+    oc, _, _ = oracle.sprinkle(d, N, seed)
+    return oracle.link(d, oc)
+
+
+def check_set(cs, ctx, s, bits, N, d):
+    n, R, queued = cs.cs_local_abundances(ctx, s)
+    h, oR = expect(bits, N)
+    assert [int(x) for x in n] == h and R == oR
+    assert 0 <= queued <= R
+    if d in (2, 4):
+        assert cs.cs_bd_action(ctx, s) == oracle.bd_action(d, N, h)
+        assert cs.cs_set_count_path(s) == cs.PATH_LOCAL
+    return queued
+
+
+@pytest.mark.parametrize("d,N,seed", [(2, 0, 1), (2, 1, 1), (2, 2, 5), (2, 63, 2), (2, 64, 3),
+                                      (2, 65, 4), (2, 300, 6), (2, 1000, 7), (2, 2049, 8),
+                                      (2, 4100, 9), (2, 9000, 10), (4, 2, 11), (4, 129, 12),
+                                      (4, 3001, 13), (4, 9500, 14)])
+def test_local_matches_oracle(cs, ctx, d, N, seed):
+    say("case local d=%d N=%d seed=%d" % (d, N, seed))
+    s = cs.cs_sprinkle(ctx, d, N, seed)
+    try:
+        cs.cs_link(ctx, s)
+        q = check_set(cs, ctx, s, oracle_bits(d, N, seed), N, d)
+        say("  queued %d" % q)
+    finally:
+        cs.cs_set_free(s)
+
+
+def injected():
+    return [
+        ("chain", ci.chain_order(3000)),
+        ("antichain", ci.antichain_order(777)),
+        # every pair is a link whose labels span the whole set: all queued,
+        # far more than the queue holds
+        ("layers2", ci.layered_order([1500, 1500])),
+        ("layers3", ci.layered_order([700, 900, 800])),
+        ("layers_thin", ci.layered_order([2, 1, 3, 2000, 3, 1, 2])),
+        ("dag", ci.random_dag_order(3000, 0.002, 5)),
+        ("union", ci.disjoint_union(ci.chain_order(1000), ci.layered_order([400, 3, 500]),
+                                    ci.random_dag_order(1200, 0.01, 6))),
+    ]
+
+
+@pytest.mark.parametrize("name,order", injected(), ids=[c[0] for c in injected()])
+def test_local_injected_orders(cs, ctx, name, order):
+    say("case local injected %s" % name)
+    N = order.shape[0]
+    bits = ci.pack_symmetric(order)
+    s = cs.cs_set_from_bitset(ctx, 2, N, bits)
+    try:
+        check_set(cs, ctx, s, bits, N, 2)
+        if name in ("chain", "antichain"):
+            assert cs.cs_bd_action(ctx, s) == 2.0 * N
+        if name == "layers2":
+            n, R, _ = cs.cs_local_abundances(ctx, s)
+            assert int(n[0]) == 1500 * 1500 and R == 1500 * 1500
+    finally:
+        cs.cs_set_free(s)
+
+
+@pytest.mark.parametrize("d,N,seed", [(2, 5000, 21), (4, 6000, 22)])
+def test_local_blocks_match_oracle(cs, ctx, d, N, seed):
+    say("case local blocks d=%d N=%d" % (d, N))
+    s = cs.cs_sprinkle(ctx, d, N, seed)
+    try:
+        cs.cs_link(ctx, s)
+        bits = oracle_bits(d, N, seed)
+        n, R, _, blocks = cs.cs_local_abundances(ctx, s, blocks=True)
+        assert blocks.shape == ((N + 63) // 64, 5)
+        tot = blocks.sum(axis=0)
+        assert list(tot[:4]) == list(n) and int(tot[4]) == R
+        for b in range(blocks.shape[0]):
+            h, oR = expect(bits, N, rows=(64 * b, min(64 * b + 64, N)))
+            assert [int(x) for x in blocks[b, :4]] == h and int(blocks[b, 4]) == oR, b
+    finally:
+        cs.cs_set_free(s)
+
+
+@pytest.mark.parametrize("chunk,extra", [(1, 0), (1, 7), (2, 7), (4, 0), (4, 6), (8, 4),
+                                         (14, 1), (14, 0), (3, 5)])
+def test_local_chunk_and_margin_settings(cs, ctx, monkeypatch, chunk, extra):
+    say("case local C=%d E=%d" % (chunk, extra))
+    monkeypatch.setenv("CS_SAT_CHUNK", str(chunk))
+    monkeypatch.setenv("CS_SAT_EXTRA", str(extra))
+    for d, N, seed in ((2, 6000, 31), (4, 4000, 32)):
+        s = cs.cs_sprinkle(ctx, d, N, seed)
+        try:
+            cs.cs_link(ctx, s)
+            check_set(cs, ctx, s, oracle_bits(d, N, seed), N, d)
+        finally:
+            cs.cs_set_free(s)
+
+
+def test_local_device_tier_any_workspace(cs):
+    """cs_count_local_dev on torch tensors, row stride wider than W: the
+    minimum workspace (no queue: the dense pass finishes every pair), a
+    small queue that overflows, and the recommended size give the oracle's
+    counts; the two calls in a row on one workspace also check that the
+    counters are cleared."""
+    import torch
+    N, seed = 7000, 41
+    say("case local device tier N=%d" % N)
+    oc, _, _ = oracle.sprinkle(2, N, seed)
+    W = cs.cs_row_words(N)
+    coords = torch.from_numpy(oc).to("cuda:0")
+    bits = torch.zeros((N, W + 8), dtype=torch.int64, device="cuda:0")
+    stream = torch.cuda.current_stream().cuda_stream
+    cs.cs_link_dev(2, N, coords.data_ptr(), bits.data_ptr(), W + 8, stream)
+    h, oR = expect(oracle.link(2, oc), N)
+    nb = (N + 63) // 64
+    minimum = 256 + 64 * nb
+    rec = cs.cs_count_local_workspace_bytes(N)
+    for wb in (minimum, minimum + 8 * 1000, rec):
+        work = torch.zeros((wb + 7) // 8, dtype=torch.int64, device="cuda:0")
+        for rep in range(2):
+            stats = torch.full((6,), -1, dtype=torch.int64, device="cuda:0")
+            cs.cs_count_local_dev(bits.data_ptr(), N, W + 8, stats.data_ptr(), work.data_ptr(), wb,
+                                  stream)
+            torch.cuda.synchronize()
+            st = stats.cpu().numpy().view(np.uint64)
+            assert [int(x) for x in st[:4]] == h and int(st[4]) == oR, (wb, rep)
+        say("  workspace %d: queued %d" % (wb, int(st[5])))
+
+
+def test_local_desitter(cs, ctx):
+    N, seed = 7000, 51
+    say("case local de Sitter N=%d" % N)
+    s = cs.cs_sprinkle_desitter(ctx, N, seed, 0.5)
+    try:
+        cs.cs_link(ctx, s)
+        oc, _, _ = oracle.sprinkle_desitter(N, seed, 0.5)
+        check_set(cs, ctx, s, oracle.link_desitter(oc), N, 2)
+    finally:
+        cs.cs_set_free(s)
+
+
+def golden(name):
+    with open(GOLDEN) as f:
+        g = json.load(f)
+    if name not in g:
+        pytest.skip("no stored oracle result for %s" % name)
+    return g[name]
+
+
+def test_local_workload_4d_16384(cs, ctx):
+    g = golden("4d_16384")
+    say("case local workload 4d_16384")
+    s = cs.cs_sprinkle(ctx, g["d"], g["N"], g["seed"])
+    try:
+        cs.cs_link(ctx, s)
+        n, R, _ = cs.cs_local_abundances(ctx, s)
+        assert [int(x) for x in n] == g["n"] and R == g["R"]
+        assert cs.cs_bd_action(ctx, s) == float.fromhex(g["S"])
+    finally:
+        cs.cs_set_free(s)
+
+
+def test_local_full_size_2d_131072(cs, ctx):
+    """The 2 GiB bench workload: N_0..N_3, R and the action equal the stored
+    oracle result; three sampled 64-label blocks equal the oracle's count
+    over the same rows of the matrix (whose bytes equal the oracle's: the
+    stored sha256)."""
+    import hashlib
+    g = golden("2d_131072")
+    N = g["N"]
+    say("case local full-size 2D N=%d" % N)
+    s = cs.cs_sprinkle(ctx, g["d"], N, g["seed"])
+    try:
+        cs.cs_link(ctx, s)
+        n, R, q, blocks = cs.cs_local_abundances(ctx, s, blocks=True)
+        say("  queued %d of %d related pairs" % (q, R))
+        assert [int(x) for x in n] == g["n"] and R == g["R"]
+        assert cs.cs_bd_action(ctx, s) == float.fromhex(g["S"])
+        bits = cs.cs_get_bitset(ctx, s)
+        assert hashlib.sha256(bits.tobytes()).hexdigest() == g["bitset_sha256"]
+        for b in (0, 977, blocks.shape[0] - 1):
+            say("  oracle block %d" % b)
+            h, oR = expect(bits, N, rows=(64 * b, 64 * b + 64))
+            assert [int(x) for x in blocks[b, :4]] == h and int(blocks[b, 4]) == oR
+    finally:
+        cs.cs_set_free(s)
