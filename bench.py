@@ -70,6 +70,7 @@ KERNEL_SOURCES = {
     "k_count_mfma<int8>": ["k_count_mfma.hip", "cs_device.h", "cs_internal.h"],
     "k_count_mfma<fp4>": ["k_count_mfma.hip", "cs_device.h", "cs_internal.h"],
     "k_count_pop": ["k_count_pop.hip", "cs_device.h", "cs_internal.h"],
+    "k_sat_tile": ["k_count_sat.hip", "cs_device.h", "cs_internal.h"],
 }
 
 
@@ -154,6 +155,51 @@ def pop_roofline(walg, t: float) -> dict:
     r["frac"] = r["achieved"] / r["peak"]
     r["traffic"] = traffic_bytes("k_count_pop")
     r["sources"] = sources_digest("k_count_pop")
+    return r
+
+
+def sat_dense_words(N: int, C: int) -> int:
+    """64-bit words the saturating count's dense step reads per pair, summed
+    over its 64x64 tiles: every word of [bi, bj] when bj - bi + 1 <= C + 2,
+    else the C-word chunk."""
+    nb = (N + 63) // 64
+    tot = 0
+    for g in range(nb):           # g = bj - bi, nb - g tiles
+        span = g + 1
+        tot += (nb - g) * (span if span <= C + 2 else C)
+    return tot
+
+
+def local_figures(cs, ctx, s, stream, ev, n_exact, R_exact, t_exact) -> dict:
+    """The saturating count (N_0..N_3 and R only) on the bench matrix: time
+    (HIP events on the library's stream, 1 warm-up + 3 timed calls) and the
+    VALU bound of its dense step (4 int32 ops per pair and word, 4096 pairs
+    per tile); the rest of the kernel (pairs continued past the window) has
+    no data-independent work count."""
+    C = int(os.environ.get("CS_SAT_CHUNK", "8"))
+    cs.cs_local_abundances(ctx, s)
+    ms = []
+    for _ in range(3):
+        ev[1].record(stream)
+        n, R, q = cs.cs_local_abundances(ctx, s)
+        ev[2].record(stream)
+        ev[2].synchronize()
+        ms.append(ev[1].elapsed_time(ev[2]))
+    t = float(np.mean(ms)) / 1000.0
+    N = WORKLOAD["N"]
+    ops = 4.0 * 4096 * sat_dense_words(N, C)
+    r = {"bound": "alu", "achieved": ops / t / 1e12, "peak": PEAK["alu_int32_ops"] / 1e12,
+         "unit": "TOP/s", "kernel": "k_sat_tile",
+         "work": "dense step only: 4 int32 ops per pair and word, 4096 pairs per 64x64 tile, "
+                 "C=%d words per tile (all of [bi, bj] when it spans <= C+2 words)" % C}
+    r["frac"] = r["achieved"] / r["peak"]
+    r["count_ms"] = {"mean": t * 1000.0, "min": float(np.min(ms)), "median": float(np.median(ms))}
+    r["pairs_per_s"] = R / t
+    r["speedup_vs_exact"] = t_exact / t
+    r["equals_exact"] = (list(n) == list(n_exact) and R == R_exact)
+    r["continued_from_hbm"] = q
+    r["sources"] = sources_digest("k_sat_tile")
+    log("local (saturating) count on the same set: %.1f ms" % (t * 1000.0))
     return r
 
 
@@ -364,6 +410,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-pop", action="store_true", help="skip the one popcount-path count")
     ap.add_argument("--no-desitter", action="store_true")
+    ap.add_argument("--no-local", action="store_true", help="skip the saturating-count leg")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers 3 times (calibrates HBM counters)")
     ap.add_argument("--serve-requests", type=int, default=10000)
@@ -440,6 +487,8 @@ def main():
         kernels["pop"]["count_ms"] = t_pop * 1000.0
         kernels["pop"]["equals_mfma"] = (list(n1) == list(n) and R1 == R and sm1 == sm)
         log("popcount path on the same set: %.1f ms" % (t_pop * 1000.0))
+    if not a.no_local:
+        kernels["local"] = local_figures(cs, ctx, s, stream, ev, n, R, t_count)
     cs.cs_set_free(s)
 
     small = small_configs(cs, ctx, stream, ev)

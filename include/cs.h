@@ -182,17 +182,16 @@ cs_status cs_interval_abundances_rows(cs_ctx* ctx, cs_set* set, int kmax,
  * pair's count stops once it reaches 4.  Every pair with m <= 3 still gets
  * its exact m, so N_0..N_3 and R are identical to cs_interval_abundances'
  * (Sec. 4.1 definition); bins above 3 and the sum of interior counts are not
- * computed.  Two passes: a dense pass over 64x64 tiles of pairs counts a few
- * words in the middle of each pair's label range (staged in LDS) and
- * finishes most pairs; the pairs still below 4 are queued in device memory
- * and finished 16 lanes per pair.  out (host, 6 words): N_0..N_3, R, and the
- * number of pairs the dense pass queued (a diagnostic).  blocks (host,
- * nullable): ceil(N/64)*5 words, for each block b of 64 labels N_0..N_3 and R
- * of the pairs i<j with i in block b.  The workspace (about N*N/32 bytes)
- * comes from the context's pool; when the budget is short a smaller queue is
- * used (pairs that do not fit are finished by the dense pass itself: same
- * result, slower).  N must be below 2^30.  Afterwards cs_bd_action uses these
- * counts and cs_set_count_path reports CS_PATH_LOCAL. */
+ * computed.  One workgroup per 64x64 tile of pairs counts a few words in the
+ * middle of the pairs' label ranges (staged in LDS), which settles most
+ * pairs, then continues the others, 16 lanes per pair, until they reach 4
+ * or their words are exhausted.  out (host, 6 words): N_0..N_3, R, and the
+ * number of pairs that had to be continued from HBM beyond the staged
+ * window (a diagnostic).  blocks (host, nullable): ceil(N/64)*5 words, for
+ * each block b of 64 labels N_0..N_3 and R of the pairs i<j with i in block
+ * b.  Device memory: 64 bytes per block of 64 labels, from the context's
+ * pool.  Afterwards cs_bd_action uses these counts and cs_set_count_path
+ * reports CS_PATH_LOCAL. */
 cs_status cs_local_abundances(cs_ctx* ctx, cs_set* set, uint64_t* out, uint64_t* blocks);
 
 /* ----------------------------------------------------------------- action */
@@ -232,13 +231,11 @@ cs_status cs_count_dev(const uint64_t* bits_dev, int64_t N,
                        void* work_dev, int path, void* hip_stream);
 
 /* Local abundances from a device matrix (the saturating count above).
- * stats_dev receives 6 uint64 words: N_0..N_3, R, pairs queued.  work_dev:
- * device scratch of work_bytes bytes, at least 256 + 64*max(1, ceil(N/64))
- * (a counter and one slot per block of 64 labels); cs_count_local_workspace_bytes(N)
- * is the recommended size (the part beyond the minimum holds the queue: a
- * smaller one gives the same result, more slowly).  Asynchronous on
- * hip_stream; CS_EINVAL for N outside [0, 2^30), a bad stride, NULL pointers
- * or a workspace below the minimum. */
+ * stats_dev receives 6 uint64 words: N_0..N_3, R, pairs continued from HBM.
+ * work_dev: device scratch of work_bytes >= cs_count_local_workspace_bytes(N)
+ * bytes (64 per block of 64 labels; per-block counters, overwritten).
+ * Asynchronous on hip_stream; CS_EINVAL for N < 0, a bad stride, NULL
+ * pointers or a workspace below the size. */
 uint64_t cs_count_local_workspace_bytes(int64_t N);
 cs_status cs_count_local_dev(const uint64_t* bits_dev, int64_t N, int64_t stride_words,
                              uint64_t* stats_dev, void* work_dev, uint64_t work_bytes,

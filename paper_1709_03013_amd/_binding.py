@@ -255,8 +255,9 @@ def cs_interval_abundances_rows(ctx: int, s: int, kmax: int = 3, path: int = PAT
 
 
 def cs_local_abundances(ctx: int, s: int, blocks: bool = False):
-    """(N_0..N_3 as uint64[4], R, pairs queued) by the saturating count; with
-    blocks=True also the per-64-label-block breakdown, uint64[ceil(N/64), 5]."""
+    """(N_0..N_3 as uint64[4], R, pairs continued from HBM) by the saturating
+    count; with blocks=True also the per-64-label-block breakdown,
+    uint64[ceil(N/64), 5]."""
     out = np.zeros(6, dtype=np.uint64)
     blk = None
     if blocks:

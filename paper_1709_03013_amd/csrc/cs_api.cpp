@@ -609,8 +609,8 @@ cs_status cs_count_dev(const uint64_t* bits_dev, int64_t N, int64_t stride_words
 static cs_status sat_params(int* C, int* E) {
   // chunk and window margin, in words; CS_SAT_CHUNK / CS_SAT_EXTRA override
   // them for tuning sweeps
-  *C = 4;
-  *E = 6;
+  *C = 8;
+  *E = 4;
   if (const char* v = std::getenv("CS_SAT_CHUNK")) *C = std::atoi(v);
   if (const char* v = std::getenv("CS_SAT_EXTRA")) *E = std::atoi(v);
   if (*C < 1 || *C > kSatWin - 2 || *E < 0 || *C + 2 * *E > kSatWin)
@@ -619,88 +619,50 @@ static cs_status sat_params(int* C, int* E) {
   return CS_OK;
 }
 
-static uint64_t sat_default_qcap(int64_t N) {
-  const uint64_t q = (uint64_t)N * (uint64_t)N / 256;
-  return q > 1024 ? q : 1024;
-}
-
-static int sat_queue_grid() {
-  static int grid = 0;
-  if (!grid) {
-    int dev = 0, cu = 0;
-    (void)hipGetDevice(&dev);
-    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0)
-      cu = 256;
-    grid = cu * 8;
-  }
-  return grid;
-}
-
-// stats: 6 device words (N_0..N_3, R, queued pairs).
-static hipError_t run_count_sat(const uint64_t* bits, int64_t N, int64_t W, uint64_t* stats,
-                                void* work, uint64_t work_bytes, int C, int E, hipStream_t st) {
-  const int64_t nb = (N + 63) / 64;
-  const uint64_t base = sat_workspace_bytes(N, 0);
-  uint64_t* qcount = (uint64_t*)work;
-  uint64_t* blk = (uint64_t*)((char*)work + 256);
-  uint64_t* queue = blk + (size_t)(nb > 0 ? nb : 1) * kSatBlkWords;
-  const uint64_t qcap = (work_bytes - base) / 8;
-  return launch_count_sat(bits, N, W, C, E, blk, qcount, queue, qcap, stats, sat_queue_grid(), st);
-}
-
 uint64_t cs_count_local_workspace_bytes(int64_t N) {
   if (N < 0) return 0;
-  return sat_workspace_bytes(N, sat_default_qcap(N));
+  return sat_workspace_bytes(N);
 }
 
 cs_status cs_count_local_dev(const uint64_t* bits_dev, int64_t N, int64_t stride_words, uint64_t* stats_dev,
                              void* work_dev, uint64_t work_bytes, void* hip_stream) {
-  if (N < 0 || N >= (1ll << 30)) return fail(CS_EINVAL, "cs_count_local_dev: N must be in [0, 2^30)");
+  if (N < 0) return fail(CS_EINVAL, "cs_count_local_dev: N < 0");
   if (!stats_dev || !work_dev || (N > 0 && !bits_dev)) return fail(CS_EINVAL, "cs_count_local_dev: NULL pointer");
   if (N > 0 && (stride_words < row_words(N) || stride_words % 4))
     return fail(CS_EINVAL, "cs_count_local_dev: stride must be >= %lld and a multiple of 4", (long long)row_words(N));
-  if (work_bytes < sat_workspace_bytes(N, 0))
-    return fail(CS_EINVAL, "cs_count_local_dev: workspace must hold at least %llu bytes",
-                (unsigned long long)sat_workspace_bytes(N, 0));
+  if (work_bytes < sat_workspace_bytes(N))
+    return fail(CS_EINVAL, "cs_count_local_dev: workspace must hold %llu bytes",
+                (unsigned long long)sat_workspace_bytes(N));
   int C, E;
   cs_status rc = sat_params(&C, &E);
   if (rc != CS_OK) return rc;
-  hipError_t e = run_count_sat(bits_dev, N, stride_words, stats_dev, work_dev, work_bytes, C, E,
-                               (hipStream_t)hip_stream);
+  hipError_t e = launch_count_sat(bits_dev, N, stride_words, C, E, (uint64_t*)work_dev, stats_dev,
+                                  (hipStream_t)hip_stream);
   return e == hipSuccess ? CS_OK : hip_fail(e, "cs_count_local_dev");
 }
 
 cs_status cs_local_abundances(cs_ctx* ctx, cs_set* s, uint64_t* out, uint64_t* blocks) {
   if (!ctx || !s || !out) return fail(CS_EINVAL, "cs_local_abundances: NULL argument");
   if (!s->linked) return fail(CS_EINVAL, "cs_local_abundances: set is not linked");
-  if (s->N >= (1ll << 30)) return fail(CS_EINVAL, "cs_local_abundances: N must be below 2^30");
   int C, E;
   cs_status rc = sat_params(&C, &E);
   if (rc != CS_OK) return rc;
   (void)hipSetDevice(ctx->device);
   const int64_t N = s->N, nb = (N + 63) / 64;
-  // the queue only speeds the count up: take a smaller one when the budget is short
-  uint64_t bytes = cs_count_local_workspace_bytes(N);
-  void* work = nullptr;
-  for (;;) {
-    work = ctx->pool.alloc(bytes);
-    const uint64_t base = sat_workspace_bytes(N, 0) + 64;  // stats live past the queue
-    if (work || bytes <= base) break;
-    bytes = std::max<uint64_t>(base, (bytes / 2) & ~(uint64_t)63);
-  }
-  if (!work) return fail(CS_ENOMEM, "cs_local_abundances: no room for the %llu-byte workspace",
-                         (unsigned long long)bytes);
-  uint64_t* stats = (uint64_t*)((char*)work + bytes - 64);
-  hipError_t e = run_count_sat(s->bits, N, s->W, stats, work, bytes - 64, C, E, ctx->stream);
+  const uint64_t wb = sat_workspace_bytes(N);
+  DevBuf work(ctx->pool, wb + 64);  // block slots, then the 6 totals
+  if (!work.p) return fail(CS_ENOMEM, "cs_local_abundances: no room for %llu bytes of counters",
+                           (unsigned long long)(wb + 64));
+  uint64_t* stats = (uint64_t*)((char*)work.p + wb);
+  hipError_t e = launch_count_sat(s->bits, N, s->W, C, E, (uint64_t*)work.p, stats, ctx->stream);
   uint64_t h[6] = {0, 0, 0, 0, 0, 0};
   std::vector<uint64_t> blk;
   if (e == hipSuccess) e = hipMemcpyAsync(h, stats, sizeof h, hipMemcpyDeviceToHost, ctx->stream);
   if (e == hipSuccess && blocks && nb > 0) {
     blk.resize((size_t)nb * kSatBlkWords);
-    e = hipMemcpyAsync(blk.data(), (char*)work + 256, blk.size() * 8, hipMemcpyDeviceToHost, ctx->stream);
+    e = hipMemcpyAsync(blk.data(), work.p, blk.size() * 8, hipMemcpyDeviceToHost, ctx->stream);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  ctx->pool.release(work);
   if (e != hipSuccess) return hip_fail(e, "cs_local_abundances");
   std::memcpy(out, h, 6 * 8);
   if (blocks)

@@ -79,10 +79,10 @@ hipError_t launch_reduce_rows(const uint64_t* rb_stats, int64_t nrb,
 // of 64x64 pairs (row blocks bi <= bj) counts the chunk [c0, c1) of C words
 // in the middle of the words strictly between its blocks, then the rest of
 // the staged window [w0, w1) (E more words on each side, clipped to
-// [bi, bj]); tiles with bj - bi + 1 <= C + 2 count all their words in the
-// chunk.  Pairs still below 4 after the window go to the queue pass.
+// [bi, bj]), then the pairs' remaining words from HBM; tiles with
+// bj - bi + 1 <= C + 2 count all their words in the chunk.
 constexpr int kSatWin = 16;      // most words a tile stages (C + 2E, or C + 2)
-constexpr int kSatBlkWords = 8;  // per row block of 64: N_0..N_3, R (one 64-byte slot)
+constexpr int kSatBlkWords = 8;  // per block of 64 labels: N_0..N_3, R, pairs continued from HBM
 struct SatWin {
   int64_t c0, c1, w0, w1;
 };
@@ -100,12 +100,11 @@ __host__ __device__ inline SatWin sat_window(int64_t bi, int64_t bj, int C, int 
   s.w1 = s.c1 + E < bj + 1 ? s.c1 + E : bj + 1;
   return s;
 }
-// Workspace: queue counter (256 B), per-block counters (nb slots), queue.
-uint64_t sat_workspace_bytes(int64_t N, uint64_t qcap);
-// out receives 6 words: N_0..N_3, R, pairs queued by the tile pass.
+// Per-block counters: one 64-byte slot per block of 64 labels.
+uint64_t sat_workspace_bytes(int64_t N);
+// out receives 6 words: N_0..N_3, R, pairs continued from HBM.
 hipError_t launch_count_sat(const uint64_t* bits, int64_t N, int64_t W, int C, int E,
-                            uint64_t* blk, uint64_t* qcount, uint64_t* queue, uint64_t qcap,
-                            uint64_t* out, int queue_grid, hipStream_t st);
+                            uint64_t* blk, uint64_t* out, hipStream_t st);
 // Validate an imported matrix: writes 0 to *bad_dev if symmetric, zero
 // diagonal, zero padding; nonzero otherwise (bad_dev zeroed by the caller).
 hipError_t launch_validate(const uint64_t* bits, int64_t N, int64_t W,

@@ -75,11 +75,11 @@ def test_argument_errors_need_no_device(lib):
 
 def test_local_count_argument_errors_need_no_device(lib, monkeypatch):
     EINVAL = lib._binding.CS_EINVAL
-    nb = lambda N: max((N + 63) // 64, 1)
-    cases = [(-1, 4, 1, 1, 10**6), (2**30, 2**24, 1, 1, 10**12),   # N outside [0, 2^30)
-             (100, 4, 0, 1, 10**6), (100, 4, 1, 0, 10**6),        # NULL stats / work
-             (100, 3, 1, 1, 10**6),                               # stride below W
-             (100, 4, 1, 1, 256 + 64 * nb(100) - 8)]              # workspace below the minimum
+    ws = lambda N: 64 * max((N + 63) // 64, 1)
+    cases = [(-1, 4, 1, 1, 10**6),                 # N < 0
+             (100, 4, 0, 1, 10**6), (100, 4, 1, 0, 10**6),   # NULL stats / work
+             (100, 3, 1, 1, 10**6), (100, 6, 1, 1, 10**6),   # stride below W, not a multiple of 4
+             (100, 4, 1, 1, ws(100) - 8)]          # workspace below the size
     for N, stride, stats, work, wb in cases:
         with pytest.raises(lib.CsError) as e:
             lib.cs_count_local_dev(1, N, stride, stats, work, wb, None)
@@ -93,9 +93,9 @@ def test_local_count_argument_errors_need_no_device(lib, monkeypatch):
         assert e.value.status == EINVAL
     monkeypatch.delenv("CS_SAT_CHUNK")
     monkeypatch.delenv("CS_SAT_EXTRA")
-    # recommended size: counter + 64-byte block slots + a queue of N*N/256 entries (>= 1024)
-    assert lib.cs_count_local_workspace_bytes(0) == 256 + 64 + 8 * 1024
-    assert lib.cs_count_local_workspace_bytes(131072) == 256 + 64 * 2048 + 8 * (131072**2 // 256)
+    assert lib.cs_count_local_workspace_bytes(0) == 64
+    assert lib.cs_count_local_workspace_bytes(131072) == 64 * 2048
+    assert lib.cs_count_local_workspace_bytes(-1) == 0
 
 
 def test_no_device_is_an_error_not_a_fallback(lib):
