@@ -62,7 +62,8 @@ PEAK = {
 TRAFFIC = {
     # FETCH_SIZE 50336831 KiB / 0.5 (the counter reads 0.5 KiB per KiB of a
     # plain copy) + WRITE_SIZE 93312 KiB / 1.0, per launch on this workload
-    "k_count_mfma_lds<fp4>": {"sources": "8d1aa427ba1529dd", "bytes": 103491937588},
+    "k_count_mfma_lds<fp4>": {"sources": "12717da311ef8625", "bytes": 105074361848},
+    "k_sat_tile": {"sources": "0df1f9ae60720e1d", "bytes": 40495281547},
 }
 KERNEL_SOURCES = {
     "k_count_mfma_lds<int8>": ["k_count_mfma.hip", "cs_device.h", "cs_internal.h"],
@@ -198,6 +199,7 @@ def local_figures(cs, ctx, s, stream, ev, n_exact, R_exact, t_exact) -> dict:
     r["speedup_vs_exact"] = t_exact / t
     r["equals_exact"] = (list(n) == list(n_exact) and R == R_exact)
     r["continued_from_hbm"] = q
+    r["traffic"] = traffic_bytes("k_sat_tile")
     r["sources"] = sources_digest("k_sat_tile")
     log("local (saturating) count on the same set: %.1f ms" % (t * 1000.0))
     return r

@@ -189,13 +189,12 @@ __global__ __launch_bounds__(256) void k_sat_tile(const uint64_t* __restrict__ b
 
   if (!chunk_all) {
     // The 16 threads tid = 16ti + tj (tj = 0..15) form a group; it takes
-    // its threads' pending pairs one at a time (lowest lane first).  Lane l
-    // of the group holds staged word kl of the window outside the chunk
-    // (even lanes above the chunk, odd lanes below, nearest first; at most
-    // E <= 7 words on each side).  Every pass clears one pending bit, so the
+    // its threads' pending pairs one at a time (lowest lane first); lane l
+    // adds the staged words l, l+16, ... of those outside the chunk.  Every
+    // pass clears one pending bit, so the
     // loop ends after at most 256 passes; its exit is uniform in the group.
-    const int l = tj, h = l >> 1, gbase = lane & 48;
-    const int kl = (l & 1) ? (h < k0 ? k0 - 1 - h : -1) : (h < nw - k1 ? k1 + h : -1);
+    const int l = tj, gbase = lane & 48;
+    const int nup = nw - k1, nout = k0 + nup;  // staged words outside the chunk
     for (;;) {
       const uint32_t gm = (uint32_t)(__ballot(pend != 0) >> gbase) & 0xffffu;
       if (!gm) break;
@@ -206,7 +205,11 @@ __global__ __launch_bounds__(256) void k_sat_tile(const uint64_t* __restrict__ b
       if (l == src) pend &= pend - 1;
       const int il = ti + 16 * (qb >> 2), jl = src + 16 * (qb & 3);
       uint32_t c = (spc >> (2 * qb)) & 3u;
-      const uint32_t p = kl >= 0 ? popc64(sI[il * kStride + kl] & sJ[jl * kStride + kl]) : 0u;
+      uint32_t p = 0;
+      for (int o = l; o < nout; o += 16) {
+        const int k = o < nup ? k1 + o : k0 - 1 - (o - nup);
+        p += popc64(sI[il * kStride + k] & sJ[jl * kStride + k]);
+      }
       c += group_sum16(p);
       if (c < 4 && !window_all) {
         cnt[5] += l == 0;
