@@ -22,9 +22,9 @@
 //  3. Related pairs still below 4 stay pending in their thread's registers
 //     and are taken, one at a time, by the thread's 16-lane group: one step
 //     over the rest of the staged window (one word per lane, outward from
-//     the chunk), then, for the few still below 4, steps
-//     of 32 words upward and 32 downward read from HBM (256-byte row
-//     segments) until the count reaches 4 or the pair's words are exhausted.
+//     the chunk), then, for the few still below 4, steps of 16 words
+//     upward and 16 downward read from HBM (128-byte row segments, two words
+//     per lane) until the count reaches 4 or the pair's words are exhausted.
 // There is no global queue or counter: a tile finishes its own pairs, and
 // its counts go to its row block's slot with one atomic add per counter.
 #include "cs_device.h"
@@ -191,8 +191,8 @@ __global__ __launch_bounds__(256) void k_sat_tile(const uint64_t* __restrict__ b
     // The 16 threads tid = 16ti + tj (tj = 0..15) form a group; it takes
     // its threads' pending pairs one at a time (lowest lane first); lane l
     // adds the staged words l, l+16, ... of those outside the chunk.  Every
-    // pass clears one pending bit, so the
-    // loop ends after at most 256 passes; its exit is uniform in the group.
+    // pass clears one pending bit, so the loop ends after at most 256
+    // passes; its exit is uniform in the group.
     const int l = tj, gbase = lane & 48;
     const int nup = nw - k1, nout = k0 + nup;  // staged words outside the chunk
     for (;;) {
