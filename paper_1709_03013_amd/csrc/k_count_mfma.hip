@@ -204,7 +204,9 @@ __device__ __forceinline__ void mfma_epilogue(const Acc (&acc)[TM][TN], const ui
         nrel += valid ? 1u : 0u;
         summ += valid ? m : 0u;
         if constexpr (FULL) {
-          atomicAdd(&lds_hist[valid && m < lb ? m : lb], 1u);
+          // related pairs only: sending the others to a spare bin made half
+          // of every tile's LDS atomics hit one address
+          if (valid && m < lb) atomicAdd(&lds_hist[m], 1u);
           if (valid && m >= lb && m <= (uint32_t)kmax)
             atomicAdd((unsigned long long*)&st[m], 1ull);
         } else {
