@@ -181,7 +181,10 @@ __device__ __forceinline__ void mfma_epilogue(const Acc (&acc)[TM][TN], const ui
   const int r32 = lane & 31, g = lane >> 5;
   uint32_t cnt[4] = {0, 0, 0, 0};
   uint32_t nrel = 0;
-  uint64_t summ = 0;
+  // a lane sums at most 16*TM*TN <= 256 interval sizes m <= N - 2; a matrix
+  // of 2^21 or more elements needs at least 2^39 bytes, more than a device
+  // holds, so the lane's sum fits 32 bits
+  uint32_t lsum = 0;
   uint64_t* st = rb_stats + BI * (int64_t)(kmax + 3);
   const uint32_t lb = (uint32_t)(kmax + 1 < kLdsBins ? kmax + 1 : kLdsBins);
 #pragma unroll
@@ -202,7 +205,7 @@ __device__ __forceinline__ void mfma_epilogue(const Acc (&acc)[TM][TN], const ui
         const bool valid = (r >> ri) & 1u;
         const uint32_t m = (uint32_t)acc[a][b][v] >> SHIFT;
         nrel += valid ? 1u : 0u;
-        summ += valid ? m : 0u;
+        lsum += valid ? m : 0u;
         if constexpr (FULL) {
           // related pairs only: sending the others to a spare bin made half
           // of every tile's LDS atomics hit one address
@@ -217,7 +220,7 @@ __device__ __forceinline__ void mfma_epilogue(const Acc (&acc)[TM][TN], const ui
     }
   }
   nrel = wave_sum_u32(nrel);
-  summ = wave_sum_u64(summ);
+  const uint64_t summ = wave_sum_u64(lsum);
   if constexpr (!FULL) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) cnt[k] = wave_sum_u32(cnt[k]);

@@ -92,6 +92,29 @@ def test_counts_match_oracle(cs, ctx, d, N, seed, path):
         cs.cs_set_free(s)
 
 
+@pytest.mark.parametrize("d,N,seed", [(2, 700, 7), (4, 1500, 8)])
+def test_every_mfma_variant_matches_oracle(cs, ctx, monkeypatch, d, N, seed):
+    """Every matrix-core kernel form selectable with CS_MFMA_VARIANT (the
+    default and the measured alternatives), int8 and fp4, N_0..N_3 and the
+    full histogram: bins, R and the sum of interior counts equal the
+    oracle's.  (The full-histogram builds of the 2x2-wave and prefetching
+    forms once returned a wrong sum of interior counts with correct bins.)"""
+    say("case every variant d=%d N=%d" % (d, N))
+    s = gpu_set(cs, ctx, d, N, seed)
+    try:
+        oc, _, _ = oracle.sprinkle(d, N, seed)
+        ob = oracle.link(d, oc)
+        want = {k: oracle.count_bits(ob, N, nbins=k + 1) for k in (3, 40, N - 2)}
+        for v in range(14):
+            monkeypatch.setenv("CS_MFMA_VARIANT", str(v))
+            for path in (2, 3):
+                for k, (h, oR, osm) in want.items():
+                    n, R, sm = cs.cs_interval_abundances(ctx, s, k, path)
+                    assert np.array_equal(n, h) and R == oR and sm == osm, (v, path, k)
+    finally:
+        cs.cs_set_free(s)
+
+
 @pytest.mark.parametrize("path", [1, 2, 3])
 @pytest.mark.parametrize("kmax", [4, 17, 200])
 @pytest.mark.parametrize("d,N,seed", [(2, 700, 31), (4, 1100, 32)])
