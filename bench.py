@@ -62,8 +62,8 @@ PEAK = {
 TRAFFIC = {
     # FETCH_SIZE 50336831 KiB / 0.5 (the counter reads 0.5 KiB per KiB of a
     # plain copy) + WRITE_SIZE 93312 KiB / 1.0, per launch on this workload
-    "k_count_mfma_lds<fp4>": {"sources": "d4be114d49976d1d", "bytes": 104565157736},
-    "k_sat_tile": {"sources": "8152c5cd84815ecb", "bytes": 40493011579},
+    "k_count_mfma_lds<fp4>": {"sources": "32e4b5e1ad42d22b", "bytes": 103375151281},
+    "k_sat_tile": {"sources": "8152c5cd84815ecb", "bytes": 40494117034},
 }
 KERNEL_SOURCES = {
     "k_count_mfma_lds<int8>": ["k_count_mfma.hip", "cs_device.h", "cs_internal.h"],
