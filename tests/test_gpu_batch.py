@@ -59,6 +59,25 @@ def test_batch_mixed_sizes_match_per_set_and_oracle(cs, ctx):
             assert r["S"] == oracle.bd_action(d, N, h)
 
 
+@pytest.mark.parametrize("mode", ["1", "3"])
+def test_batch_count_path_settings_agree(cs, ctx, monkeypatch, mode):
+    """CS_BATCH_PATH=1 (every set on the popcount kernel) and 3 (the tuner's
+    choice per set) give the default batch's results, which equal the
+    per-set path.  A fresh context per setting: plans are cached per
+    context and batch shape."""
+    say("case batch path mode %s" % mode)
+    plan = MIXED[:12]
+    refs = [per_set(cs, ctx, *p) for p in plan]
+    monkeypatch.setenv("CS_BATCH_PATH", mode)
+    c2 = cs.cs_create(0, 0, None)
+    try:
+        res = cs.cs_batch_run(c2, plan)
+    finally:
+        cs.cs_destroy(c2)
+    for p, r, ref in zip(plan, res, refs):
+        assert r == ref, (mode, p, r, ref)
+
+
 def test_graph_replays_with_eager_work_between(cs, ctx):
     say("case batch replays")
     plan = [(2, 500, 1), (4, 700, 2), (2, 1200, 3), (4, 9000, 4)]

@@ -96,6 +96,20 @@ def test_full_size_sampled_row_blocks(cs, ctx):
         cs.cs_set_free(s)
 
 
+@pytest.mark.parametrize("variant", ["1", "2", "4"])
+def test_link_variants_match_oracle(cs, ctx, monkeypatch, variant):
+    monkeypatch.setenv("CS_LINK_VARIANT", variant)
+    N, seed = 3000, 41
+    say("case desitter link variant %s" % variant)
+    s = cs.cs_sprinkle_desitter(ctx, N, seed, ETA0)
+    try:
+        cs.cs_link(ctx, s)
+        oc, _, _ = oracle.sprinkle_desitter(N, seed, ETA0)
+        assert np.array_equal(cs.cs_get_bitset(ctx, s), oracle.link_desitter(oc))
+    finally:
+        cs.cs_set_free(s)
+
+
 def test_rejects_bad_eta0(cs, ctx):
     for bad in (0.0, -0.1, math.pi / 4, 1.0, float("nan")):
         with pytest.raises(cs.CsError):

@@ -92,6 +92,22 @@ def test_counts_match_oracle(cs, ctx, d, N, seed, path):
         cs.cs_set_free(s)
 
 
+@pytest.mark.parametrize("variant", ["1", "2", "4"])
+def test_every_link_variant_matches_oracle(cs, ctx, monkeypatch, variant):
+    """The link kernel's one-, two- and four-words-per-pass forms
+    (CS_LINK_VARIANT; four is the default) write the oracle's matrix, 2D and
+    4D, ragged sizes."""
+    monkeypatch.setenv("CS_LINK_VARIANT", variant)
+    for d, N, seed in ((2, 2049, 8), (2, 4100, 9), (4, 3001, 11), (4, 300, 12)):
+        say("case link variant %s d=%d N=%d" % (variant, d, N))
+        s = gpu_set(cs, ctx, d, N, seed)
+        try:
+            oc, _, _ = oracle.sprinkle(d, N, seed)
+            assert np.array_equal(cs.cs_get_bitset(ctx, s), oracle.link(d, oc))
+        finally:
+            cs.cs_set_free(s)
+
+
 @pytest.mark.parametrize("d,N,seed", [(2, 700, 7), (4, 1500, 8)])
 def test_every_mfma_variant_matches_oracle(cs, ctx, monkeypatch, d, N, seed):
     """Every matrix-core kernel form selectable with CS_MFMA_VARIANT (the
