@@ -250,6 +250,44 @@ def test_device_pointer_tier_with_torch(cs):
     assert list(st[:4]) == list(h) and st[4] == R and st[5] == sm
 
 
+@pytest.mark.parametrize("path", [1, 2, 3])
+@pytest.mark.parametrize("kmax", [3, 50])
+def test_device_pointer_tier_paths(cs, path, kmax):
+    """cs_count_dev on a torch-owned matrix (stride wider than W) with each
+    count path and a histogram past bin 3: the oracle's bins, R and sum."""
+    import torch
+    d, N, seed = 2, 3000, 52
+    say("case device tier path=%d kmax=%d" % (path, kmax))
+    oc, _, _ = oracle.sprinkle(d, N, seed)
+    ob = oracle.link(d, oc)
+    W = cs.cs_row_words(N)
+    bits = torch.zeros((N, W + 12), dtype=torch.int64)
+    bits[:, :W] = torch.from_numpy(ob.view(np.int64))
+    bits = bits.to("cuda:0")
+    stats = torch.zeros(kmax + 3, dtype=torch.int64, device="cuda:0")
+    work = torch.zeros(cs.cs_count_workspace_bytes(N, kmax) // 8, dtype=torch.int64, device="cuda:0")
+    stream = torch.cuda.current_stream().cuda_stream
+    cs.cs_count_dev(bits.data_ptr(), N, W + 12, kmax, stats.data_ptr(), work.data_ptr(), path, stream)
+    torch.cuda.synchronize()
+    h, R, sm = oracle.count_bits(ob, N, nbins=kmax + 1)
+    st = stats.cpu().numpy().view(np.uint64)
+    assert np.array_equal(st[:kmax + 1], h) and st[kmax + 1] == R and st[kmax + 2] == sm
+
+
+def test_histogram_longer_than_the_set(cs, ctx):
+    """kmax beyond N - 2: the bins past the largest possible interval are 0."""
+    N, seed, kmax = 60, 53, 200
+    s = gpu_set(cs, ctx, 2, N, seed)
+    try:
+        oc, _, _ = oracle.sprinkle(2, N, seed)
+        h, R, sm = oracle.count_bits(oracle.link(2, oc), N, nbins=N - 1)
+        for path in (1, 2, 3):
+            n, gR, gsm = cs.cs_interval_abundances(ctx, s, kmax, path)
+            assert np.array_equal(n[:N - 1], h) and not n[N - 1:].any() and gR == R and gsm == sm
+    finally:
+        cs.cs_set_free(s)
+
+
 # ----------------------------------------------------------- error handling
 def test_errors(cs, ctx):
     with pytest.raises(cs.CsError):
