@@ -418,8 +418,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=10000)
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see the sharding paragraph in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(its sharding is a design, not code); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
