@@ -187,6 +187,29 @@ def test_local_desitter(cs, ctx):
         cs.cs_set_free(s)
 
 
+def test_random_sets_every_count_path(cs, ctx):
+    """Forty seeded random sets (d in {2, 4}, N in [2, 3000]): the three
+    exact paths and the saturating count against the oracle."""
+    rng = np.random.default_rng(20261202)
+    for k in range(40):
+        d = int(rng.choice([2, 4]))
+        N = int(rng.integers(2, 3001))
+        seed = int(rng.integers(1, 2**63))
+        say("case random d=%d N=%d seed=%d" % (d, N, seed))
+        s = cs.cs_sprinkle(ctx, d, N, seed)
+        try:
+            cs.cs_link(ctx, s)
+            ob = oracle_bits(d, N, seed)
+            h, R, sm = oracle.count_bits(ob, N, nbins=4)
+            for path in (1, 2, 3):
+                n, gR, gsm = cs.cs_interval_abundances(ctx, s, 3, path)
+                assert list(n) == list(h) and gR == R and gsm == sm, (d, N, seed, path)
+            nl, Rl, _ = cs.cs_local_abundances(ctx, s)
+            assert list(nl) == list(h) and Rl == R, (d, N, seed)
+        finally:
+            cs.cs_set_free(s)
+
+
 def golden(name):
     with open(GOLDEN) as f:
         g = json.load(f)
