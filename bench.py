@@ -64,6 +64,7 @@ TRAFFIC = {
     # plain copy) + WRITE_SIZE 93312 KiB / 1.0, per launch on this workload
     "k_count_mfma_lds<fp4>": {"sources": "32e4b5e1ad42d22b", "bytes": 103375151281},
     "k_sat_tile": {"sources": "8152c5cd84815ecb", "bytes": 40494117034},
+    "k_count_pop": {"sources": "a7be8e83898c0202", "bytes": 2541606105923},
 }
 KERNEL_SOURCES = {
     "k_count_mfma_lds<int8>": ["k_count_mfma.hip", "cs_device.h", "cs_internal.h"],
