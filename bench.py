@@ -255,8 +255,15 @@ def cpu_baseline(budget_s: float = 12.0):
         log("cpu_baseline: rows %d..%d, %.1f s so far" % (lo, lo + 63, t_count))
         if t_count > budget_s:
             break
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {
         "value": pairs / t_count, "unit": "interval pairs/s", "cores": nthreads, "kind": "oracle",
+        "cpu": cpu, "affinity": len(os.sched_getaffinity(0)),
         "sample": "%d rows (64-row blocks evenly spread over the N=131072 2D set, seed 3): interval "
                   "counts of all %d related pairs (i,j) with i in the sample, %.1f s; the oracle's "
                   "full link (%.1f s) not included" % (rows, pairs, t_count, t_link),
