@@ -191,7 +191,10 @@ cs_status cs_interval_abundances_rows(cs_ctx* ctx, cs_set* set, int kmax,
  * each block b of 64 labels N_0..N_3 and R of the pairs i<j with i in block
  * b.  Device memory: 64 bytes per block of 64 labels, from the context's
  * pool.  Afterwards cs_bd_action uses these counts and cs_set_count_path
- * reports CS_PATH_LOCAL. */
+ * reports CS_PATH_LOCAL.  The middle chunk (C words) and the staged margin
+ * on each side (E words) default to 8 and 4; the environment variables
+ * CS_SAT_CHUNK and CS_SAT_EXTRA override them (1 <= C <= 14, E >= 0,
+ * C + 2E <= 16, else CS_EINVAL); the result does not depend on them. */
 cs_status cs_local_abundances(cs_ctx* ctx, cs_set* set, uint64_t* out, uint64_t* blocks);
 
 /* ----------------------------------------------------------------- action */
