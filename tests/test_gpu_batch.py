@@ -78,6 +78,24 @@ def test_batch_count_path_settings_agree(cs, ctx, monkeypatch, mode):
         assert r == ref, (mode, p, r, ref)
 
 
+def test_ensemble_means_match_2d_expectations(cs, ctx):
+    """8192 2D diamonds of N = 256 in one batch: the sample means of
+    N_0..N_3 equal the exact expectations over random 2D orders (a rational
+    closed form, pinned against all orders of N <= 7 in the oracle tests),
+    and the mean action equals 2 (Eq. 4 in expectation), each within five
+    standard errors of the sample."""
+    from test_oracle_count import expected_abundance_2d
+    N, sets = 256, 8192
+    say("case ensemble means N=%d sets=%d" % (N, sets))
+    res = cs.cs_batch_run(ctx, [(2, N, 700000 + k) for k in range(sets)])
+    n = np.array([r["n"] for r in res], dtype=np.float64)
+    S = np.array([r["S"] for r in res])
+    se = n.std(axis=0, ddof=1) / np.sqrt(sets)
+    exp = np.array([float(expected_abundance_2d(N, k)) for k in range(4)])
+    assert np.all(np.abs(n.mean(axis=0) - exp) < 5 * se), (n.mean(axis=0), exp, se)
+    assert abs(S.mean() - 2.0) < 5 * S.std(ddof=1) / np.sqrt(sets), (S.mean(), S.std())
+
+
 def test_graph_replays_with_eager_work_between(cs, ctx):
     say("case batch replays")
     plan = [(2, 500, 1), (4, 700, 2), (2, 1200, 3), (4, 9000, 4)]
