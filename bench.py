@@ -335,22 +335,36 @@ def small_configs(cs, ctx, stream, ev):
     return out
 
 
-def desitter(cs, ctx, N=32768, graphs=10, eta0=0.5, eps=2.0**-6):
-    """The paper's de Sitter experiment (Sec. 6.1): ten (1+1) de Sitter slabs
-    of N elements at eta0, the smeared action with eps, against the
-    continuum value 4 pi tan(eta0)."""
-    S = []
-    t0 = time.time()
-    for g in range(graphs):
-        s = cs.cs_sprinkle_desitter(ctx, N, 1000 + g, eta0)
-        cs.cs_link(ctx, s)
-        S.append(cs.cs_smeared_action(ctx, s, eps))
-        cs.cs_set_free(s)
-    t = time.time() - t0
+def desitter(cs, ctx, N=32768, graphs=10, eta0=0.5, eps=2.0**-6,
+             sweep=((1024, 10), (4096, 10), (16384, 10), (65536, 5), (131072, 3))):
+    """The paper's de Sitter experiment (Sec. 6.1): (1+1) de Sitter slabs at
+    eta0, the smeared action with eps against the continuum value
+    4 pi tan(eta0).  Ten graphs at N (timed), then the convergence sweep over
+    (N, graphs) from 2^10 to 2^17 elements."""
+    def run(n, g, seed0):
+        S = []
+        t0 = time.time()
+        for k in range(g):
+            s = cs.cs_sprinkle_desitter(ctx, n, seed0 + k, eta0)
+            cs.cs_link(ctx, s)
+            S.append(cs.cs_smeared_action(ctx, s, eps))
+            cs.cs_set_free(s)
+        t = time.time() - t0
+        return S, t
+
+    S, t = run(N, graphs, 1000)
     log("desitter: %d graphs of N=%d in %.2f s" % (graphs, N, t))
+    by_n = []
+    for n, g in sweep:
+        Sn, tn = run(n, g, 2000)
+        by_n.append({"N": n, "graphs": g, "seeds": "2000..%d" % (2000 + g - 1),
+                     "S_eps_mean": float(np.mean(Sn)),
+                     "S_eps_sd": float(np.std(Sn, ddof=1)) if g > 1 else None,
+                     "graphs_per_s": g / tn})
+        log("desitter sweep: N=%d, %d graphs, S_eps %.3f, %.2f s" % (n, g, np.mean(Sn), tn))
     return {"N": N, "graphs": graphs, "eta0": eta0, "eps": eps, "seeds": "1000..%d" % (1000 + graphs - 1),
             "S_eps_mean": float(np.mean(S)), "S_eps_sd": float(np.std(S, ddof=1)),
-            "S_EH": 4 * math.pi * math.tan(eta0), "graphs_per_s": graphs / t}
+            "S_EH": 4 * math.pi * math.tan(eta0), "graphs_per_s": graphs / t, "by_N": by_n}
 
 
 def served(cs, nreq=10000, slots=4, budget_gib=32.0, load=0.7):
