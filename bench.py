@@ -336,7 +336,7 @@ def small_configs(cs, ctx, stream, ev):
 
 
 def desitter(cs, ctx, N=32768, graphs=10, eta0=0.5, eps=2.0**-6,
-             sweep=((1024, 10), (4096, 10), (16384, 10), (65536, 5), (131072, 3))):
+             sweep=((1024, 10), (4096, 10), (16384, 10), (65536, 10), (131072, 10))):
     """The paper's de Sitter experiment (Sec. 6.1): (1+1) de Sitter slabs at
     eta0, the smeared action with eps against the continuum value
     4 pi tan(eta0).  Ten graphs at N (timed), then the convergence sweep over
