@@ -11,8 +11,10 @@ What fixes the expected values, independently of the oracle's code:
   compared with the oracle run on every permutation;
 * the 3-chain identity: sum of m over related pairs = sum over k of
   #below(k) * #above(k) for a transitive relation;
-* the action of a chain and of an antichain (Eq. 4 in 2D; the 4D weights are
-  the reading of the cited BD reference, pinned only by these closed forms).
+* the action of a chain and of an antichain, and of hand-counted layered
+  orders; Eq. 4's 2D weights as printed; the 4D weights (the reading of the
+  cited BD reference) and their index convention by the moment identities
+  that Eq. 4's weights satisfy in 2D, written for d = 4.
 """
 import itertools
 import math
@@ -260,3 +262,107 @@ def test_action_chain_from_counts(oracle_lib):
     bits = ci.pack_symmetric(ci.chain_order(N))
     h, _, _ = oracle_lib.count_bits(bits, N, nbins=4)
     assert oracle_lib.bd_action(2, N, h) == 2.0 * N
+
+
+# ------------------------------------------- the action's weights and indices
+def _bracket_weights(oracle_lib, d):
+    """The integer weights c_k the oracle's action gives N_k (k = 0..3), read
+    back from S for N = 0 and a unit abundance vector, and its prefactor
+    (S of one isolated element).  S = prefactor * (N + sum_k c_k N_k)."""
+    pref = oracle_lib.bd_action(d, 1, [0, 0, 0, 0])
+    c = []
+    for k in range(4):
+        e = [0, 0, 0, 0]
+        e[k] = 1
+        ratio = oracle_lib.bd_action(d, 0, e) / pref
+        assert abs(ratio - round(ratio)) < 1e-12
+        c.append(int(round(ratio)))
+    return pref, c
+
+
+def _tau2_moment(c, d, shift=0):
+    """sum_k c_k Gamma(k+s+1+2/d) / (Gamma(1+2/d) (k+s)!), exactly, for the
+    weights applied to N_{k+s}.  With a Poisson sprinkling of density rho, the
+    expected number of intervals of k interior elements in a pair whose
+    interval has volume v is weighted by e^{-x} x^k / k! (x = rho v); this sum
+    is the integral over x in (0, inf) of x^{2/d} e^{-x} sum_k c_k x^k / k!,
+    the moment carrying the squared proper time (v grows as tau^d)."""
+    a = Fraction(2, d)
+    tot = Fraction(0)
+    for k, ck in enumerate(c):
+        j = k + shift
+        g = Fraction(1)
+        for t in range(1, j + 1):           # Gamma(j+1+a) / (Gamma(1+a) j!)
+            g *= (t + a) / t
+        tot += ck * g
+    return tot
+
+
+def test_action_weights_2d_are_eq4(oracle_lib):
+    # Eq. 4 as printed: S = 2 (N - 2 n_1 + 4 n_2 - 2 n_3), n_i = N_{i-1}
+    pref, c = _bracket_weights(oracle_lib, 2)
+    assert pref == 2.0 and c == [-2, 4, -2, 0]
+    # the two moment identities Eq. 4's weights satisfy (d = 2: the squared
+    # proper-time moment is sum_k c_k (k+1))
+    assert sum(c) == 0
+    assert _tau2_moment(c, 2) == 0
+    assert sum(ck * (k + 1) for k, ck in enumerate(c)) == 0
+
+
+def test_action_weights_4d_moments_and_index(oracle_lib):
+    """The 4D bracket (reading of the BD weights the paper cites for Eq. 4)
+    against identities that fix its index convention: a chain of N elements
+    gives N - 1 (sum c_k = 0, sum k c_k = 1), and the d = 4 form of the
+    squared-proper-time moment that Eq. 4's weights satisfy in 2D vanishes:
+    -1 + 9 (3/2) - 16 (15/8) + 8 (35/16) = 0.  Applied one bin off (to
+    N_1..N_4) the same weights give 1/16, so a shifted bracket fails here.  The prefactor 4/sqrt 6 is the
+    literature's and stays unpinned by the paper."""
+    pref, c = _bracket_weights(oracle_lib, 4)
+    assert pref == 4.0 / math.sqrt(6.0)
+    assert c == [-1, 9, -16, 8]
+    assert sum(c) == 0
+    assert sum(k * ck for k, ck in enumerate(c)) == 1
+    assert _tau2_moment(c, 4) == 0
+    assert _tau2_moment(c, 4, shift=1) == Fraction(1, 16)
+    # a sign flip of one weight, or the 2D weights, break it too
+    for k in range(4):
+        flipped = list(c)
+        flipped[k] = -flipped[k]
+        assert _tau2_moment(flipped, 4) != 0
+    assert _tau2_moment([-2, 4, -2, 0], 4) != 0
+
+
+def _hand_layered_11211():
+    """Complete layered order x1 < x2 < {a, b} < y1 < y2 (layer sizes
+    1,1,2,1,1), counted by hand: links x1x2, x2a, x2b, ay1, by1, y1y2 (N_0=6);
+    one element inside: x1-a, x1-b (x2), a-y2, b-y2 (y1) (N_1=4); two: x2-y1
+    ({a,b}) (N_2=1); three: x1-y1 ({x2,a,b}), x2-y2 ({a,b,y1}) (N_3=2); four:
+    x1-y2 (N_4=1).  R = 14 (all 15 pairs but a-b)."""
+    return ci.layered_order([1, 1, 2, 1, 1]), [6, 4, 1, 2, 1]
+
+
+def _hand_boolean_lattice_3():
+    """Subsets of {0,1,2} ordered by strict inclusion (8 elements, labels in
+    order of size then value): a pair A < B has 2^|B-A| - 2 elements inside.
+    |B-A| = 1: 12 pairs (N_0); 2: 6 pairs (N_2); 3: one pair (N_6)."""
+    sets = sorted(range(8), key=lambda s: (bin(s).count("1"), s))
+    prec = np.array([[a != b and (a & b) == a for b in sets] for a in sets])
+    return prec, [12, 0, 6, 0, 0, 0, 1]
+
+
+@pytest.mark.parametrize("make", [_hand_layered_11211, _hand_boolean_lattice_3])
+def test_action_on_hand_counted_orders(oracle_lib, make):
+    """Small orders with distinct, hand-counted N_0..N_4: the oracle's counts
+    equal the hand counts and its 2D/4D actions equal the brackets written
+    out with them, so an index shift (weights on N_1..N_4) changes S here."""
+    prec, hand = make()
+    N = prec.shape[0]
+    h, R, _ = oracle_lib.count_bits(ci.pack_symmetric(prec), N, nbins=len(hand))
+    assert [int(x) for x in h] == hand and R == sum(hand)
+    n = hand[:4]
+    S2 = 2.0 * (N - 2 * n[0] + 4 * n[1] - 2 * n[2])
+    K4 = N - n[0] + 9 * n[1] - 16 * n[2] + 8 * n[3]
+    assert oracle_lib.bd_action(2, N, h[:4]) == S2
+    assert oracle_lib.bd_action(4, N, h[:4]) == (4.0 / math.sqrt(6.0)) * K4
+    shifted = N - hand[1] + 9 * hand[2] - 16 * hand[3] + 8 * hand[4]
+    assert shifted != K4
