@@ -1,7 +1,7 @@
 """Benchmark: interval pairs/s and BD actions/s on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--path P] [--no-cpu] [--no-batch]
-                    [--no-serve] [--no-pop] [--no-span] [--no-desitter]
+                    [--no-serve] [--no-pop] [--no-span] [--no-desitter] [--no-local]
 
 One step = the whole hot path on the 2D flat causal diamond with N = 131072
 elements (seed 3): sprinkle + time sort, link (2 GiB packed matrix), interval
@@ -13,18 +13,23 @@ per second of the whole step.
 Also reported on the same line:
   * roofline: the counting kernel (the dominant one), timed with HIP events
     on the library's stream over the timed region;
-  * cpu_baseline: the CPU oracle's counting rate on a bounded row sample of
-    the same set, on this host's cores;
-  * kernels: the link kernel's HBM rate, and the popcount kernel on the same
-    matrix (once) with its integer-ALU fraction;
-  * other_configs: the 2D N=1024 and 4D N=16384 single-set workloads;
+  * kernels: the link kernel against its vector-ALU bound and HBM, and the
+    popcount and int8 matrix-core count on the same matrix (once), each
+    against its own peak, and the saturating count of N_0..N_3;
+  * other_configs: the 2D N=1024 and 4D N=16384 single-set workloads, with
+    the same per-kernel figures;
   * ensemble: 512 sets (N uniform in [256, 4096], d in {2, 4}) as BD
-    actions/s, batched (one cs_batch_run) vs per-set (a loop of cs_* calls);
+    actions/s, batched (one cs_batch_run, tuned on its first call) vs per-set
+    (a loop of cs_* calls), the tuner's choices, the batched count against the
+    fp4 peak, and every set checked against the stored oracle results;
   * desitter: ten (1+1) de Sitter slabs of 2^15 elements (eta0 = 0.5), the
-    smeared action at eps = 2^-6 against 4 pi tan(eta0);
+    smeared action at eps = 2^-6 against 4 pi tan(eta0), and a sweep over N;
   * served: 10,000 queued requests (N log-uniform in [512, 32768]) with
     Poisson arrivals at 0.7x the saturated rate, p50/p99 latency and
-    actions/s, under a 32 GiB and a 1 GiB budget.
+    actions/s, under a 32 GiB and a 1 GiB budget; every 50th result checked
+    against the stored oracle results;
+  * cpu_baseline: the CPU oracle's counting rate on fixed row samples of the
+    2D N=131072 and 4D N=16384 sets, 3 warm-ups then min and median of 5.
 
 Protocol: W warm-up steps (default 3), then K timed steps (default 5);
 ms_per_step is their mean, count/link kernel times are also given as min and
@@ -48,31 +53,26 @@ WORKLOAD = dict(d=2, N=131072, seed=3)
 PEAK = {
     "int8_mfma_tops": 5.0e15,      # dense int8 MFMA, ops/s
     "fp4_mfma_flops": 10.1e15,     # dense fp4 MFMA, flop/s
-    "alu_int32_ops": 256 * 64 * 2.4e9,  # 256 CU x 64 lanes x 2.4 GHz, 32-bit VALU ops/s
+    "alu_ops": 256 * 64 * 2.4e9,   # 256 CU x 64 lanes x 2.4 GHz: one 32-bit op (or one
+                                   # binary64 add, multiply or compare) per lane per cycle
     "hbm_bytes": 8.0e12,
 }
+GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_reference.json")
 
 
-# HBM traffic per launch of a count kernel on this workload: rocprofv3 --pmc
-# FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each divided by what the same
-# counter reads per byte of a plain device-to-device copy.  Keyed by the
-# SHA-256 of the kernel's source files when the counters were taken: after
-# any change to them the figure no longer describes the kernel and is
+# HBM traffic per launch of a kernel on the 2D N=131072 workload: rocprofv3
+# --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each divided by what
+# the same counter reads per byte of a plain device-to-device copy.  Keyed
+# by the SHA-256 of the kernel's source files when the counters were taken:
+# after any change to them the figure no longer describes the kernel and is
 # reported as null.
-TRAFFIC = {
-    # FETCH_SIZE 50336831 KiB / 0.5 (the counter reads 0.5 KiB per KiB of a
-    # plain copy) + WRITE_SIZE 93312 KiB / 1.0, per launch on this workload
-    "k_count_mfma_lds<fp4>": {"sources": "32e4b5e1ad42d22b", "bytes": 103375151281},
-    "k_sat_tile": {"sources": "8152c5cd84815ecb", "bytes": 40494117034},
-    "k_count_pop": {"sources": "a7be8e83898c0202", "bytes": 2541606105923},
-}
+TRAFFIC = {}
 KERNEL_SOURCES = {
     "k_count_mfma_lds<int8>": ["k_count_mfma.hip", "cs_device.h", "cs_internal.h"],
     "k_count_mfma_lds<fp4>": ["k_count_mfma.hip", "cs_device.h", "cs_internal.h"],
-    "k_count_mfma<int8>": ["k_count_mfma.hip", "cs_device.h", "cs_internal.h"],
-    "k_count_mfma<fp4>": ["k_count_mfma.hip", "cs_device.h", "cs_internal.h"],
     "k_count_pop": ["k_count_pop.hip", "cs_device.h", "cs_internal.h"],
     "k_sat_tile": ["k_count_sat.hip", "cs_device.h", "cs_internal.h"],
+    "k_link": ["k_link.hip", "cs_internal.h"],
 }
 
 
@@ -94,6 +94,11 @@ def traffic_bytes(kernel: str):
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def stored(name):
+    with open(GOLDEN) as f:
+        return json.load(f)[name]
 
 
 def span_words(bits: np.ndarray, N: int) -> int:
@@ -128,20 +133,21 @@ def span_words(bits: np.ndarray, N: int) -> int:
     return tot
 
 
+def with_frac(r: dict) -> dict:
+    r["frac"] = r["achieved"] / r["peak"]
+    return r
+
+
 def mfma_roofline(N: int, t: float, fp4: bool) -> dict:
     """Matrix-core count: 2*C(N,3) operations (one multiply and one add per
     triple i < k < j) in t seconds against the dense peak of its operand type."""
     ops = 2.0 * math.comb(N, 3)
-    # the library's kernel shape (CS_MFMA_VARIANT, default 12: LDS-staged, 2x4 waves,
-    # 4 stages, weighted spreading, XCD-grouped tile order, unscaled fp4 encoding)
-    lds = int(os.environ.get("CS_MFMA_VARIANT", "12")) >= 2
-    kernel = ("k_count_mfma_lds" if lds else "k_count_mfma") + ("<fp4>" if fp4 else "<int8>")
-    r = {"bound": "mfma", "achieved": ops / t / 1e12,
-         "peak": (PEAK["fp4_mfma_flops"] if fp4 else PEAK["int8_mfma_tops"]) / 1e12,
-         "unit": "TFLOP/s", "kernel": kernel,
-         "work": "2*C(N,3) operations (multiply + add per triple i<k<j), %s operands"
-                 % ("fp4 e2m1 0/1" if fp4 else "int8 0/1 (an int8 operation counted as a flop)")}
-    r["frac"] = r["achieved"] / r["peak"]
+    kernel = "k_count_mfma_lds" + ("<fp4>" if fp4 else "<int8>")
+    r = with_frac({"bound": "mfma", "achieved": ops / t / 1e12,
+                   "peak": (PEAK["fp4_mfma_flops"] if fp4 else PEAK["int8_mfma_tops"]) / 1e12,
+                   "unit": "TFLOP/s" if fp4 else "TOP/s", "kernel": kernel,
+                   "work": "2*C(N,3) operations (multiply + add per triple i<k<j), %s operands"
+                           % ("fp4 e2m1 0/1" if fp4 else "int8 0/1")})
     r["traffic"] = traffic_bytes(kernel)
     r["sources"] = sources_digest(kernel)
     return r
@@ -151,12 +157,35 @@ def pop_roofline(walg, t: float) -> dict:
     """Popcount count: 4 int32 VALU operations (2 AND, 2 bit counts) per
     64-bit word of every related pair's span."""
     ops = 4.0 * walg if walg else float("nan")
-    r = {"bound": "alu", "achieved": ops / t / 1e12, "peak": PEAK["alu_int32_ops"] / 1e12,
-         "unit": "TOP/s", "kernel": "k_count_pop",
-         "work": "4 int32 ops per 64-bit word of the span of every related pair (W_alg=%s)" % walg}
-    r["frac"] = r["achieved"] / r["peak"]
+    r = with_frac({"bound": "alu", "achieved": ops / t / 1e12, "peak": PEAK["alu_ops"] / 1e12,
+                   "unit": "TOP/s", "kernel": "k_count_pop",
+                   "work": "4 int32 ops per 64-bit word of the span of every related pair (W_alg=%s)" % walg})
     r["traffic"] = traffic_bytes("k_count_pop")
     r["sources"] = sources_digest("k_count_pop")
+    return r
+
+
+# binary64 operations per relation test: 2D 2 compares; 4D 4 subtractions,
+# 4 multiplications, 2 additions and a compare; de Sitter 6 multiplications,
+# 2 subtractions, 2 additions (with the 1 +) and 2 compares (the absolute
+# values are free operand modifiers)
+LINK_OPS = {2: 2, 4: 11, 3: 12}
+
+
+def link_figures(d: int, N: int, W: int, link_ms) -> dict:
+    """Link kernel: C(N,2) relation tests (each pair once) against the vector
+    ALU, and N*W*8 bytes of matrix written against HBM."""
+    t = float(np.mean(link_ms)) / 1000.0
+    byt = N * W * 8
+    ops = LINK_OPS[d] * math.comb(N, 2)
+    r = with_frac({"bound": "alu", "achieved": ops / t / 1e12, "peak": PEAK["alu_ops"] / 1e12,
+                   "unit": "TOP/s", "kernel": "k_link",
+                   "work": "C(N,2) relation tests x %d binary64 ops" % LINK_OPS[d]})
+    r["hbm"] = {"achieved": byt / t / 1e9, "peak": PEAK["hbm_bytes"] / 1e9, "unit": "GB/s",
+                "frac": byt / t / PEAK["hbm_bytes"], "bytes": byt}
+    r["link_ms"] = {"mean": t * 1000.0, "min": float(np.min(link_ms)), "median": float(np.median(link_ms))}
+    r["traffic"] = traffic_bytes("k_link")
+    r["sources"] = sources_digest("k_link")
     return r
 
 
@@ -172,29 +201,34 @@ def sat_dense_words(N: int, C: int) -> int:
     return tot
 
 
-def local_figures(cs, ctx, s, stream, ev, n_exact, R_exact, t_exact) -> dict:
-    """The saturating count (N_0..N_3 and R only) on the bench matrix: time
-    (HIP events on the library's stream, 1 warm-up + 3 timed calls) and the
-    VALU bound of its dense step (4 int32 ops per pair and word, 4096 pairs
-    per tile); the rest of the kernel (pairs continued past the window) has
-    no data-independent work count."""
-    C = int(os.environ.get("CS_SAT_CHUNK", "8"))
-    cs.cs_local_abundances(ctx, s)
+def timed(stream, ev, fn, reps=3):
+    """ms of fn() on the library's stream: one warm-up, `reps` timed."""
+    fn()
     ms = []
-    for _ in range(3):
+    out = None
+    for _ in range(reps):
         ev[1].record(stream)
-        n, R, q = cs.cs_local_abundances(ctx, s)
+        out = fn()
         ev[2].record(stream)
         ev[2].synchronize()
         ms.append(ev[1].elapsed_time(ev[2]))
+    return ms, out
+
+
+def local_figures(cs, ctx, s, stream, ev, n_exact, R_exact, t_exact) -> dict:
+    """The saturating count (N_0..N_3 and R only) on the bench matrix: time
+    and the VALU bound of its dense step (4 int32 ops per pair and word, 4096
+    pairs per tile); the rest of the kernel (pairs continued past the window)
+    has no data-independent work count."""
+    C = 8  # the library's middle chunk (words)
+    ms, (n, R, q) = timed(stream, ev, lambda: cs.cs_local_abundances(ctx, s))
     t = float(np.mean(ms)) / 1000.0
     N = WORKLOAD["N"]
     ops = 4.0 * 4096 * sat_dense_words(N, C)
-    r = {"bound": "alu", "achieved": ops / t / 1e12, "peak": PEAK["alu_int32_ops"] / 1e12,
-         "unit": "TOP/s", "kernel": "k_sat_tile",
-         "work": "dense step only: 4 int32 ops per pair and word, 4096 pairs per 64x64 tile, "
-                 "C=%d words per tile (all of [bi, bj] when it spans <= C+2 words)" % C}
-    r["frac"] = r["achieved"] / r["peak"]
+    r = with_frac({"bound": "alu", "achieved": ops / t / 1e12, "peak": PEAK["alu_ops"] / 1e12,
+                   "unit": "TOP/s", "kernel": "k_sat_tile",
+                   "work": "dense step only: 4 int32 ops per pair and word, 4096 pairs per 64x64 tile, "
+                           "C=%d words per tile (all of [bi, bj] when it spans <= C+2 words)" % C})
     r["count_ms"] = {"mean": t * 1000.0, "min": float(np.min(ms)), "median": float(np.median(ms))}
     r["pairs_per_s"] = R / t
     r["speedup_vs_exact"] = t_exact / t
@@ -206,21 +240,9 @@ def local_figures(cs, ctx, s, stream, ev, n_exact, R_exact, t_exact) -> dict:
     return r
 
 
-def link_figures(N: int, W: int, link_ms) -> dict:
-    """Link kernel: N*W*8 bytes of matrix written (coordinate reads are
-    N*16 bytes and negligible) per launch."""
-    t = float(np.mean(link_ms)) / 1000.0
-    byt = N * W * 8
-    return {"bound": "hbm", "achieved": byt / t / 1e9, "peak": PEAK["hbm_bytes"] / 1e9,
-            "unit": "GB/s", "frac": byt / t / PEAK["hbm_bytes"], "bytes": byt,
-            "link_ms": {"mean": t * 1000.0, "min": float(np.min(link_ms)),
-                        "median": float(np.median(link_ms))}}
-
-
-def run_step(cs, ctx, ev, stream, path):
+def run_step(cs, ctx, ev, stream, path, d, N, seed):
     """One pass of the hot path; ev[0..2] bracket link and count on the
     library's stream."""
-    d, N, seed = WORKLOAD["d"], WORKLOAD["N"], WORKLOAD["seed"]
     s = cs.cs_sprinkle(ctx, d, N, seed)
     ev[0].record(stream)
     cs.cs_link(ctx, s)
@@ -231,42 +253,58 @@ def run_step(cs, ctx, ev, stream, path):
     return s, n, R, sm, S
 
 
-def cpu_baseline(budget_s: float = 12.0):
+def cpu_sample(d, N, seed, rows, reps_warm=3, reps=5):
+    """The oracle's interval count over fixed row blocks of one sprinkled set:
+    3 warm-ups, then min and median of 5 (the oracle's own link is done once,
+    outside the timing)."""
     import oracle
-    d, N, seed = WORKLOAD["d"], WORKLOAD["N"], WORKLOAD["seed"]
-    t0 = time.time()
     coords, _, _ = oracle.sprinkle(d, N, seed)
+    t0 = time.time()
     bits = oracle.link(d, coords)
     t_link = time.time() - t0
-    nthreads = oracle.num_threads()
-    # evenly spaced 64-row blocks until the time budget is used
-    starts = [int(x) for x in np.linspace(0, N - 64, 64)]
-    order = [starts[k] for k in np.random.default_rng(0).permutation(len(starts))]
+    ts = []
     pairs = 0
-    rows = 0
-    t_count = 0.0
-    log("cpu_baseline: oracle link of N=%d done in %.1f s on %d threads" % (N, t_link, nthreads))
-    for lo in order:
-        t1 = time.time()
-        _, R, _ = oracle.count_bits(bits, N, nbins=4, rows=(lo, lo + 64))
-        t_count += time.time() - t1
-        pairs += R
-        rows += 64
-        log("cpu_baseline: rows %d..%d, %.1f s so far" % (lo, lo + 63, t_count))
-        if t_count > budget_s:
-            break
+    for k in range(reps_warm + reps):
+        t1 = time.perf_counter()
+        p = 0
+        for lo in rows:
+            _, R, _ = oracle.count_bits(bits, N, nbins=4, rows=(lo, min(lo + 64, N)))
+            p += R
+        dt = time.perf_counter() - t1
+        if k >= reps_warm:
+            ts.append(dt)
+        pairs = p
+    return {"pairs": pairs, "rows": 64 * len(rows), "s_min": min(ts), "s_median": float(np.median(ts)),
+            "pairs_per_s": pairs / min(ts), "oracle_link_s": t_link}
+
+
+def cpu_baseline():
+    import oracle
+    nthreads = oracle.num_threads()
     cpu = "unknown"
     try:
         with open("/proc/cpuinfo") as f:
             cpu = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
     except (OSError, StopIteration):
         pass
+    # fixed samples: 64-row blocks evenly spread over each set
+    c3_rows = [int(x) for x in np.linspace(0, 131072 - 64, 4)]
+    c2_rows = [int(x) for x in np.linspace(0, 16384 - 64, 16)]
+    log("cpu_baseline: 2D N=131072 sample")
+    c3 = cpu_sample(2, 131072, 3, c3_rows)
+    log("cpu_baseline: 4D N=16384 sample")
+    c2 = cpu_sample(4, 16384, 2, c2_rows)
     return {
-        "value": pairs / t_count, "unit": "interval pairs/s", "cores": nthreads, "kind": "oracle",
+        "value": c3["pairs_per_s"], "unit": "interval pairs/s", "cores": nthreads, "kind": "oracle",
         "cpu": cpu, "affinity": len(os.sched_getaffinity(0)),
-        "sample": "%d rows (64-row blocks evenly spread over the N=131072 2D set, seed 3): interval "
-                  "counts of all %d related pairs (i,j) with i in the sample, %.1f s; the oracle's "
-                  "full link (%.1f s) not included" % (rows, pairs, t_count, t_link),
+        "protocol": "3 warm-ups, then min (value) and median of 5 timed repetitions",
+        "sample": "2D N=131072 seed 3: the interval counts of all %d related pairs (i,j) with i in "
+                  "4 fixed 64-row blocks (rows %s), min %.2f s, median %.2f s; the oracle's link "
+                  "(%.1f s) not included" % (c3["pairs"], c3_rows, c3["s_min"], c3["s_median"],
+                                             c3["oracle_link_s"]),
+        "c2_4d_16384": {"pairs_per_s": c2["pairs_per_s"], "pairs": c2["pairs"], "s_min": c2["s_min"],
+                        "s_median": c2["s_median"],
+                        "sample": "16 fixed 64-row blocks evenly spread over the set"},
     }
 
 
@@ -274,15 +312,35 @@ def ensemble(cs, ctx, nsets=512):
     import causet_inputs as ci
     plan = ci.ensemble_plan(nsets)
     out = {}
+    ref = stored("ensemble_512") if nsets == 512 else None
     try:
-        cs.cs_batch_run(ctx, plan)  # warm-up (graph capture, tuning)
-        log("ensemble: warm-up batch done")
         t0 = time.time()
-        res = cs.cs_batch_run(ctx, plan)
-        tb = time.time() - t0
-        log("ensemble: batched %d sets in %.3f s" % (nsets, tb))
+        cs.cs_batch_run(ctx, plan)  # first call of the shape: plan, graph capture, tuning
+        out["first_call_s"] = time.time() - t0
+        log("ensemble: first (tuning) batch done in %.3f s" % out["first_call_s"])
+        ts = []
+        res = None
+        for _ in range(5):
+            t0 = time.perf_counter()
+            res = cs.cs_batch_run(ctx, plan)
+            ts.append(time.perf_counter() - t0)
+        tb = min(ts)
+        log("ensemble: batched %d sets in %.3f ms (min of 5)" % (nsets, tb * 1e3))
         out["batched_actions_per_s"] = nsets / tb
-        out["batched_s"] = tb
+        out["batched_s"] = {"min": tb, "median": float(np.median(ts))}
+        info = cs.cs_batch_last_info(ctx)
+        out["tuner"] = info
+        useful = sum(2.0 * math.comb(N, 3) for _, N, _ in plan)
+        t_count = info["count_ms_tuned"] / 1e3
+        out["count_roofline"] = with_frac({
+            "bound": "mfma", "achieved": useful / t_count / 1e12, "peak": PEAK["fp4_mfma_flops"] / 1e12,
+            "unit": "TFLOP/s", "kernel": "k_batch_count_mfma*/k_batch_count_pop",
+            "work": "sum over the sets of 2*C(N,3) (multiply + add per triple), against the fp4 peak",
+            "count_ms_tuned": info["count_ms_tuned"], "count_ms_untuned": info["count_ms_untuned"]})
+        if ref is not None:
+            out["batched_equals_oracle"] = all(
+                r["n"] == o["n"] and r["R"] == o["R"] and r["summ"] == o["summ"] and r["S"] == float.fromhex(o["S"])
+                for r, o in zip(res, ref))
     except cs.CsError as e:
         out["batched_error"] = str(e)
         res = None
@@ -306,32 +364,36 @@ def ensemble(cs, ctx, nsets=512):
     return out
 
 
-def small_configs(cs, ctx, stream, ev):
-    """The other two single-set workloads: 2D N=1024 (seed 1) and 4D N=16384
-    (seed 2).  Whole step and count call timed, 3 warm-ups, 5 timed."""
-    out = {}
-    for name, d, N, seed in (("2d_1024", 2, 1024, 1), ("4d_16384", 4, 16384, 2)):
-        steps, counts = [], []
-        for k in range(8):
-            t0 = time.perf_counter()
-            s = cs.cs_sprinkle(ctx, d, N, seed)
-            cs.cs_link(ctx, s)
-            ev[1].record(stream)
-            n, R, sm = cs.cs_interval_abundances(ctx, s, 3, 0)
-            ev[2].record(stream)
-            S = cs.cs_bd_action(ctx, s)
-            ev[2].synchronize()
-            if k >= 3:
-                steps.append((time.perf_counter() - t0) * 1e3)
-                counts.append(ev[1].elapsed_time(ev[2]))
-            path = cs.cs_set_count_path(s)
+def single_set_figures(cs, ctx, stream, ev, name, d, N, seed, steps=5, warm=3):
+    """One single-set workload: whole step and link/count kernels, 3 warm-ups,
+    5 timed, each kernel against its own roofline."""
+    step_ms, link_ms, count_ms = [], [], []
+    for k in range(warm + steps):
+        t0 = time.perf_counter()
+        s, n, R, sm, S = run_step(cs, ctx, ev, stream, 0, d, N, seed)
+        ev[2].synchronize()
+        if k >= warm:
+            step_ms.append((time.perf_counter() - t0) * 1e3)
+            link_ms.append(ev[0].elapsed_time(ev[1]))
+            count_ms.append(ev[1].elapsed_time(ev[2]))
+        path = cs.cs_set_count_path(s)
+        if k + 1 < warm + steps:
             cs.cs_set_free(s)
-        out[name] = {"N": N, "d": d, "related_pairs": R, "abundances": [int(x) for x in n], "action": S,
-                     "count_path": {1: "pop", 2: "mfma_int8", 3: "mfma_fp4"}[path],
-                     "ms_per_step": float(np.mean(steps)), "count_ms": float(np.mean(counts)),
-                     "pairs_per_s": R / (float(np.mean(steps)) / 1e3)}
-        log("%s: step %.3f ms, count %.3f ms (%s)" % (name, out[name]["ms_per_step"], out[name]["count_ms"],
-                                                     out[name]["count_path"]))
+    W = cs.cs_row_words(N)
+    t_count = float(np.mean(count_ms)) / 1e3
+    if path in (2, 3):
+        count = mfma_roofline(N, t_count, path == 3)
+    else:
+        count = pop_roofline(span_words(cs.cs_get_bitset(ctx, s), N), t_count)
+    count["count_ms"] = {"mean": t_count * 1e3, "min": float(np.min(count_ms)),
+                         "median": float(np.median(count_ms))}
+    cs.cs_set_free(s)
+    out = {"N": N, "d": d, "seed": seed, "related_pairs": R, "abundances": [int(x) for x in n],
+           "action": S, "count_path": {1: "pop", 2: "mfma_int8", 3: "mfma_fp4"}[path],
+           "ms_per_step": float(np.mean(step_ms)), "pairs_per_s": R / (float(np.mean(step_ms)) / 1e3),
+           "count": count, "link": link_figures(d, N, W, link_ms)}
+    log("%s: step %.3f ms, link %.3f ms, count %.3f ms (%s)" % (name, out["ms_per_step"], np.mean(link_ms),
+                                                                 t_count * 1e3, out["count_path"]))
     return out
 
 
@@ -371,17 +433,25 @@ def served(cs, nreq=10000, slots=4, budget_gib=32.0, load=0.7):
     """Served stream: requests with Poisson arrivals (N log-uniform in
     [512, 32768], d in {2, 4}).  The saturated rate is measured first on a
     burst of the first 1500 requests; the timed run offers all requests at
-    `load` times that rate.  Half the budget may hold resident matrices."""
+    `load` times that rate.  Half the budget may hold resident matrices.
+    Every 50th result of the timed run is checked against the stored oracle
+    results."""
     import causet_inputs as ci
     plan = ci.request_plan(nreq)
+    sample = stored("served_sample") if nreq == 10000 else None
+    check = {o["q"]: o for o in sample["results"]} if sample else {}
     ctx = cs.cs_create(0, int(budget_gib * 2**30), None)
     try:
         cs.cs_queue_start(ctx, slots, int(budget_gib * 2**30 / 2))
 
-        def drive(reqs, arrivals):
+        def drive(reqs, arrivals, keep):
+            # submit every request whose arrival time has come, then take
+            # finished requests in completion order (cs_queue_next), waiting
+            # at most until the next arrival
             t0 = time.perf_counter()
             pending = {}
             lat = []
+            kept = {}
             k = 0
             done = 0
             while done < len(reqs):
@@ -390,34 +460,38 @@ def served(cs, nreq=10000, slots=4, budget_gib=32.0, load=0.7):
                     d, N, seed = reqs[k]
                     pending[cs.cs_queue_submit(ctx, d, N, seed)] = k
                     k += 1
-                for t in list(pending):
-                    r = cs.cs_queue_poll(ctx, t)
-                    if r is not None:
-                        res, tm = r
-                        assert res["status"] == 0
-                        lat.append(tm[2])
-                        del pending[t]
-                        done += 1
-                        if done % 1000 == 0:
-                            log("served (%g GiB): %d/%d done, %.1f s" % (budget_gib, done, len(reqs),
-                                                                        time.perf_counter() - t0))
-                if k < len(reqs) and arrivals is not None:
-                    time.sleep(max(0.0, min(0.0005, arrivals[k] - (time.perf_counter() - t0))))
-            return time.perf_counter() - t0, np.array(lat)
+                wait = 0.01 if k >= len(reqs) or arrivals is None else max(0.0, arrivals[k] - now)
+                r = cs.cs_queue_next(ctx, wait)
+                while r is not None:
+                    t, res, tm = r
+                    assert res["status"] == 0
+                    lat.append(tm[2])
+                    q = pending.pop(t)
+                    if q in keep:
+                        kept[q] = res
+                    done += 1
+                    if done % 1000 == 0:
+                        log("served (%g GiB): %d/%d done, %.1f s" % (budget_gib, done, len(reqs),
+                                                                    time.perf_counter() - t0))
+                    r = cs.cs_queue_next(ctx, 0.0)
+            return time.perf_counter() - t0, np.array(lat), kept
 
         reqs = [(d, N, seed) for _, d, N, seed in plan]
         cal_n = min(1500, nreq)
-        t_cal, _ = drive(reqs[:cal_n], None)
+        t_cal, _, _ = drive(reqs[:cal_n], None, set())
         sat = cal_n / t_cal
         log("served (%g GiB): saturated %.0f actions/s on a burst of %d" % (budget_gib, sat, cal_n))
         rate = load * sat
         gaps = np.array([a for a, *_ in plan])
         gaps = gaps / gaps[-1] * (nreq / rate)  # rescale the Poisson arrivals to `rate`
-        t_run, lat = drive(reqs, gaps)
+        t_run, lat, kept = drive(reqs, gaps, set(check))
+        ok = all(kept[q]["n"] == o["n"] and kept[q]["R"] == o["R"] and kept[q]["summ"] == o["summ"]
+                 and kept[q]["S"] == float.fromhex(o["S"]) for q, o in check.items())
         return {"requests": nreq, "slots": slots, "hbm_budget_gib": budget_gib,
                 "saturated_actions_per_s": sat, "offered_rate_per_s": rate,
                 "actions_per_s": nreq / t_run, "p50_ms": float(np.percentile(lat, 50) * 1e3),
-                "p99_ms": float(np.percentile(lat, 99) * 1e3), "wall_s": t_run}
+                "p99_ms": float(np.percentile(lat, 99) * 1e3), "wall_s": t_run,
+                "checked_against_oracle": len(check), "equals_oracle": ok if check else None}
     finally:
         cs.cs_destroy(ctx)
 
@@ -427,12 +501,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--path", type=int, default=0, help="0 auto, 1 popcount, 2 MFMA")
+    ap.add_argument("--path", type=int, default=0, help="0 auto, 1 popcount, 2 MFMA int8, 3 MFMA fp4")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-span", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--no-pop", action="store_true", help="skip the one popcount-path count")
+    ap.add_argument("--no-pop", action="store_true", help="skip the popcount and int8 counts of C3")
     ap.add_argument("--no-desitter", action="store_true")
     ap.add_argument("--no-local", action="store_true", help="skip the saturating-count leg")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -448,7 +522,7 @@ def main():
 
     if a.copy_probe:
         # a plain device-to-device copy of known size: what FETCH_SIZE and
-        # WRITE_SIZE read for it calibrates those counters for the count kernel
+        # WRITE_SIZE read for it calibrates those counters for the kernels
         n = a.copy_probe // 8
         src = torch.arange(n, dtype=torch.int64, device="cuda:0")
         dst = torch.empty_like(src)
@@ -464,9 +538,10 @@ def main():
     stream = torch.cuda.Stream(device=0)
     ctx = cs.cs_create(0, 0, stream.cuda_stream)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    d, N, seed = WORKLOAD["d"], WORKLOAD["N"], WORKLOAD["seed"]
 
     for _ in range(a.warmup):
-        s, *_ = run_step(cs, ctx, ev, stream, a.path)
+        s, *_ = run_step(cs, ctx, ev, stream, a.path, d, N, seed)
         cs.cs_set_free(s)
     torch.cuda.synchronize()
     log("warm-up done (%d steps)" % a.warmup)
@@ -474,7 +549,7 @@ def main():
     t0 = time.perf_counter()
     for k in range(a.steps):
         ts = time.perf_counter()
-        s, n, R, sm, S = run_step(cs, ctx, ev, stream, a.path)
+        s, n, R, sm, S = run_step(cs, ctx, ev, stream, a.path, d, N, seed)
         ev[2].synchronize()
         step_ms.append((time.perf_counter() - ts) * 1000.0)
         link_ms.append(ev[0].elapsed_time(ev[1]))
@@ -485,12 +560,12 @@ def main():
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1000.0 / a.steps
     log("step %.1f ms, count %s ms, link %s ms" % (ms_step, ["%.1f" % x for x in count_ms],
-                                                  ["%.2f" % x for x in link_ms]))
+                                                  ["%.3f" % x for x in link_ms]))
 
-    N = WORKLOAD["N"]
     W = cs.cs_row_words(N)
     path_used = cs.cs_set_count_path(s)
     t_count = float(np.mean(count_ms)) / 1000.0
+    walg = None
     if path_used in (2, 3):
         roof = mfma_roofline(N, t_count, path_used == 3)
     else:
@@ -498,32 +573,38 @@ def main():
         roof = pop_roofline(walg, t_count)
     roof["count_ms"] = {"mean": float(np.mean(count_ms)), "min": float(np.min(count_ms)),
                         "median": float(np.median(count_ms))}
-    kernels = {"link": link_figures(N, W, link_ms)}
-    if not a.no_pop and path_used != 1:
-        # the popcount kernel on the same matrix, once, for its ALU fraction
-        ev[1].record(stream)
-        n1, R1, sm1 = cs.cs_interval_abundances(ctx, s, 3, 1)
-        ev[2].record(stream)
-        ev[2].synchronize()
-        t_pop = ev[1].elapsed_time(ev[2]) / 1000.0
-        walg = None if a.no_span else span_words(cs.cs_get_bitset(ctx, s), N)
-        kernels["pop"] = pop_roofline(walg, t_pop)
-        kernels["pop"]["count_ms"] = t_pop * 1000.0
-        kernels["pop"]["equals_mfma"] = (list(n1) == list(n) and R1 == R and sm1 == sm)
-        log("popcount path on the same set: %.1f ms" % (t_pop * 1000.0))
+    kernels = {"link": link_figures(d, N, W, link_ms)}
+    if not a.no_pop:
+        # the other count paths on the same matrix, once each
+        for p, name in ((1, "pop"), (2, "mfma_int8"), (3, "mfma_fp4")):
+            if p == path_used:
+                continue
+            ms, (n1, R1, sm1) = timed(stream, ev, lambda: cs.cs_interval_abundances(ctx, s, 3, p), reps=1)
+            tp = ms[0] / 1000.0
+            if p == 1:
+                if walg is None and not a.no_span:
+                    walg = span_words(cs.cs_get_bitset(ctx, s), N)
+                fig = pop_roofline(walg, tp)
+            else:
+                fig = mfma_roofline(N, tp, p == 3)
+            fig["count_ms"] = tp * 1000.0
+            fig["equals_default_path"] = (list(n1) == list(n) and R1 == R and sm1 == sm)
+            kernels[name] = fig
+            log("%s count on the same set: %.1f ms" % (name, tp * 1000.0))
     if not a.no_local:
         kernels["local"] = local_figures(cs, ctx, s, stream, ev, n, R, t_count)
     cs.cs_set_free(s)
 
-    small = small_configs(cs, ctx, stream, ev)
+    small = {"2d_1024": single_set_figures(cs, ctx, stream, ev, "2d_1024", 2, 1024, 1),
+             "4d_16384": single_set_figures(cs, ctx, stream, ev, "4d_16384", 4, 16384, 2)}
     ens = None if a.no_batch else ensemble(cs, ctx)
     dsx = None if a.no_desitter else desitter(cs, ctx)
     srv = None
     if not a.no_serve:
         srv = {"unbound_32gib": served(cs, a.serve_requests, budget_gib=32.0),
                "bound_1gib": served(cs, a.serve_requests, budget_gib=1.0)}
-    cpu = None if a.no_cpu else cpu_baseline()
     cs.cs_destroy(ctx)
+    cpu = None if a.no_cpu else cpu_baseline()
 
     rec = {
         "metric": "interval pairs/s & BD actions/s: batched vs per-set, 2D N=2^17",

@@ -191,10 +191,8 @@ cs_status cs_interval_abundances_rows(cs_ctx* ctx, cs_set* set, int kmax,
  * each block b of 64 labels N_0..N_3 and R of the pairs i<j with i in block
  * b.  Device memory: 64 bytes per block of 64 labels, from the context's
  * pool.  Afterwards cs_bd_action uses these counts and cs_set_count_path
- * reports CS_PATH_LOCAL.  The middle chunk (C words) and the staged margin
- * on each side (E words) default to 8 and 4; the environment variables
- * CS_SAT_CHUNK and CS_SAT_EXTRA override them (1 <= C <= 14, E >= 0,
- * C + 2E <= 16, else CS_EINVAL); the result does not depend on them. */
+ * reports CS_PATH_LOCAL.  The middle chunk is 8 words and the staged
+ * margin on each side 4 words; the result does not depend on them. */
 cs_status cs_local_abundances(cs_ctx* ctx, cs_set* set, uint64_t* out, uint64_t* blocks);
 
 /* ----------------------------------------------------------------- action */
@@ -264,16 +262,34 @@ typedef struct {
 #define CS_BATCH_NMAX 16384
 /* Run a whole ensemble (the Monte Carlo use of Sec. 1.2): every set is
  * sprinkled, sorted, linked, counted and its action evaluated, with all sets
- * sharing each launch (the counting is one persistent launch over the (set,
- * tile) work items of every set, sorted longest first and dealt to a fixed
- * grid in snake order; sets of 64 or more elements use the fp4 matrix-core
- * count).  The launch sequence is captured once per batch shape in a hipGraph
- * and replayed.  out[s] is the result of reqs[s]; identical to running the
- * set alone.  A request with d not 2 or 4 or N outside [0, CS_BATCH_NMAX]
- * gets status CS_EINVAL in its own result.  Device memory comes from the
- * context's pool (CS_ENOMEM if the batch does not fit the budget). */
+ * sharing each launch; the counting is one persistent launch per count
+ * kernel over the (set, tile) work items of every set, sorted longest first
+ * and dealt to a fixed grid in snake order.  The launch sequence is captured
+ * once per batch shape (the list of (d, N)) in a hipGraph and replayed.  The
+ * first call of a shape also tunes it: for each (d, ceil(log2 N)) group not
+ * seen before on the context, the popcount kernel and the matrix-core kernel
+ * (fp4) with 128- and 256-row tiles are timed on that group's sets and the
+ * fastest is kept (every candidate must give identical counts), then each
+ * kernel's grid is timed; see cs_batch_last_info.  out[s] is the result of
+ * reqs[s]; identical to running the set alone.  A request with d not 2 or 4
+ * or N outside [0, CS_BATCH_NMAX] gets status CS_EINVAL in its own result.
+ * Device memory comes from the context's pool (CS_ENOMEM if the batch does
+ * not fit the budget). */
 cs_status cs_batch_run(cs_ctx* ctx, int nsets, const cs_req* reqs,
                        cs_result* out);
+
+/* What the batch tuner chose for the most recent cs_batch_run on the
+ * context: the number of sets counted by each kernel (64-row popcount
+ * tiles, 256- and 128-row matrix-core tiles), each kernel's persistent grid
+ * (workgroups; 0 if unused), and the count kernels' time on that batch's
+ * matrices with the first-guess choices and with the tuned ones (ms, best
+ * of three, measured when the shape was first run). */
+typedef struct {
+  int32_t sets_pop, sets_mfma256, sets_mfma128;
+  int32_t grid_pop, grid_mfma256, grid_mfma128;
+  double count_ms_untuned, count_ms_tuned;
+} cs_batch_info;
+cs_status cs_batch_last_info(cs_ctx* ctx, cs_batch_info* out);
 
 /* ---------------------------------------------------------- queued serving */
 /* Continuous-batching request server on the context.  Requests are admitted
@@ -289,6 +305,13 @@ cs_status cs_queue_submit(cs_ctx* ctx, const cs_req* req, uint64_t* ticket);
  * unknown ticket.  timing (nullable, 3 doubles): submit->admit, admit->done,
  * submit->done in seconds. */
 cs_status cs_queue_poll(cs_ctx* ctx, uint64_t ticket, cs_result* out,
+                        double* timing);
+/* The next finished request, in completion order, whatever its ticket:
+ * waits up to timeout_s seconds (0 = do not wait) and returns CS_OK with
+ * *ticket, *out and timing (nullable, as for cs_queue_poll) filled, or
+ * CS_EBUSY if none finished in time.  A request is returned once, by either
+ * call. */
+cs_status cs_queue_next(cs_ctx* ctx, double timeout_s, uint64_t* ticket, cs_result* out,
                         double* timing);
 /* Block until every submitted request is done. */
 cs_status cs_queue_drain(cs_ctx* ctx);

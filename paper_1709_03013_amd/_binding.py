@@ -43,6 +43,16 @@ class cs_result(ctypes.Structure):
                 "S": float(self.S), "status": int(self.status)}
 
 
+class cs_batch_info(ctypes.Structure):
+    _fields_ = [("sets_pop", ctypes.c_int32), ("sets_mfma256", ctypes.c_int32),
+                ("sets_mfma128", ctypes.c_int32), ("grid_pop", ctypes.c_int32),
+                ("grid_mfma256", ctypes.c_int32), ("grid_mfma128", ctypes.c_int32),
+                ("count_ms_untuned", ctypes.c_double), ("count_ms_tuned", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _vp = ctypes.c_void_p
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -82,9 +92,11 @@ _SIGS = {
     "cs_count_local_dev": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int64, _vp, _vp,
                                           ctypes.c_uint64, _vp]),
     "cs_batch_run": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(cs_req), ctypes.POINTER(cs_result)]),
+    "cs_batch_last_info": (ctypes.c_int, [_vp, ctypes.POINTER(cs_batch_info)]),
     "cs_queue_start": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_uint64]),
     "cs_queue_submit": (ctypes.c_int, [_vp, ctypes.POINTER(cs_req), _u64p]),
     "cs_queue_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(cs_result), _dp]),
+    "cs_queue_next": (ctypes.c_int, [_vp, ctypes.c_double, _u64p, ctypes.POINTER(cs_result), _dp]),
     "cs_queue_drain": (ctypes.c_int, [_vp]),
     "cs_queue_stop": (ctypes.c_int, [_vp]),
 }
@@ -322,6 +334,12 @@ def cs_batch_run(ctx: int, plan):
     return [out[k].as_dict() for k in range(len(plan))]
 
 
+def cs_batch_last_info(ctx: int) -> dict:
+    info = cs_batch_info()
+    _check(lib().cs_batch_last_info(ctx, ctypes.byref(info)))
+    return info.as_dict()
+
+
 def cs_queue_start(ctx: int, slots: int = 4, resident_budget: int = 0):
     _check(lib().cs_queue_start(ctx, slots, resident_budget))
 
@@ -342,6 +360,19 @@ def cs_queue_poll(ctx: int, ticket: int):
         return None
     _check(rc)
     return out.as_dict(), (tm[0], tm[1], tm[2])
+
+
+def cs_queue_next(ctx: int, timeout_s: float = 0.0):
+    """None if nothing finished within timeout_s, else (ticket, result dict,
+    (wait_s, run_s, total_s)) of the next finished request."""
+    t = ctypes.c_uint64()
+    out = cs_result()
+    tm = (ctypes.c_double * 3)()
+    rc = lib().cs_queue_next(ctx, float(timeout_s), ctypes.byref(t), ctypes.byref(out), tm)
+    if rc == CS_EBUSY:
+        return None
+    _check(rc)
+    return int(t.value), out.as_dict(), (tm[0], tm[1], tm[2])
 
 
 def cs_queue_drain(ctx: int):

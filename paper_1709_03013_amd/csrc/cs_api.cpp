@@ -606,19 +606,6 @@ cs_status cs_count_dev(const uint64_t* bits_dev, int64_t N, int64_t stride_words
 
 // ---- local abundances by the saturating count -------------------------------
 
-static cs_status sat_params(int* C, int* E) {
-  // chunk and window margin, in words; CS_SAT_CHUNK / CS_SAT_EXTRA override
-  // them for tuning sweeps
-  *C = 8;
-  *E = 4;
-  if (const char* v = std::getenv("CS_SAT_CHUNK")) *C = std::atoi(v);
-  if (const char* v = std::getenv("CS_SAT_EXTRA")) *E = std::atoi(v);
-  if (*C < 1 || *C > kSatWin - 2 || *E < 0 || *C + 2 * *E > kSatWin)
-    return fail(CS_EINVAL, "saturating count: chunk %d and margin %d must satisfy 1 <= C <= %d, "
-                "E >= 0, C + 2E <= %d", *C, *E, kSatWin - 2, kSatWin);
-  return CS_OK;
-}
-
 uint64_t cs_count_local_workspace_bytes(int64_t N) {
   if (N < 0) return 0;
   return sat_workspace_bytes(N);
@@ -633,10 +620,7 @@ cs_status cs_count_local_dev(const uint64_t* bits_dev, int64_t N, int64_t stride
   if (work_bytes < sat_workspace_bytes(N))
     return fail(CS_EINVAL, "cs_count_local_dev: workspace must hold %llu bytes",
                 (unsigned long long)sat_workspace_bytes(N));
-  int C, E;
-  cs_status rc = sat_params(&C, &E);
-  if (rc != CS_OK) return rc;
-  hipError_t e = launch_count_sat(bits_dev, N, stride_words, C, E, (uint64_t*)work_dev, stats_dev,
+  hipError_t e = launch_count_sat(bits_dev, N, stride_words, kSatChunk, kSatMargin, (uint64_t*)work_dev, stats_dev,
                                   (hipStream_t)hip_stream);
   return e == hipSuccess ? CS_OK : hip_fail(e, "cs_count_local_dev");
 }
@@ -644,9 +628,6 @@ cs_status cs_count_local_dev(const uint64_t* bits_dev, int64_t N, int64_t stride
 cs_status cs_local_abundances(cs_ctx* ctx, cs_set* s, uint64_t* out, uint64_t* blocks) {
   if (!ctx || !s || !out) return fail(CS_EINVAL, "cs_local_abundances: NULL argument");
   if (!s->linked) return fail(CS_EINVAL, "cs_local_abundances: set is not linked");
-  int C, E;
-  cs_status rc = sat_params(&C, &E);
-  if (rc != CS_OK) return rc;
   (void)hipSetDevice(ctx->device);
   const int64_t N = s->N, nb = (N + 63) / 64;
   const uint64_t wb = sat_workspace_bytes(N);
@@ -654,7 +635,7 @@ cs_status cs_local_abundances(cs_ctx* ctx, cs_set* s, uint64_t* out, uint64_t* b
   if (!work.p) return fail(CS_ENOMEM, "cs_local_abundances: no room for %llu bytes of counters",
                            (unsigned long long)(wb + 64));
   uint64_t* stats = (uint64_t*)((char*)work.p + wb);
-  hipError_t e = launch_count_sat(s->bits, N, s->W, C, E, (uint64_t*)work.p, stats, ctx->stream);
+  hipError_t e = launch_count_sat(s->bits, N, s->W, kSatChunk, kSatMargin, (uint64_t*)work.p, stats, ctx->stream);
   uint64_t h[6] = {0, 0, 0, 0, 0, 0};
   std::vector<uint64_t> blk;
   if (e == hipSuccess) e = hipMemcpyAsync(h, stats, sizeof h, hipMemcpyDeviceToHost, ctx->stream);

@@ -60,6 +60,12 @@ constexpr int kLinkDeSitter = 3;
 hipError_t launch_link(int d, int64_t N, const double* coords, uint64_t* bits,
                        int64_t W, hipStream_t st);
 
+// Link tiles of one set in a batch: *nrt row tiles, *nct column tiles; the
+// set's items are (ti, tk) for every ti < *nrt and batch_link_first_col(ti)
+// <= tk < *nct.  Returns their number.
+int64_t batch_link_tiles(int64_t N, int64_t W, int64_t* nrt, int64_t* nct);
+int64_t batch_link_first_col(int64_t ti);
+
 // Fill n uint64 words with v (a kernel, so it can sit in a captured graph).
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t st);
 
@@ -82,6 +88,12 @@ hipError_t launch_reduce_rows(const uint64_t* rb_stats, int64_t nrb,
 // [bi, bj]), then the pairs' remaining words from HBM; tiles with
 // bj - bi + 1 <= C + 2 count all their words in the chunk.
 constexpr int kSatWin = 16;      // most words a tile stages (C + 2E, or C + 2)
+// C and E of the library's count: at 2D N = 2^17 (C, E) = (4, 6) took 35 ms,
+// (8, 4) 32 ms, (12, 2) 32 ms, (14, 1) 33 ms; every setting gives the same
+// counts (the staged window only decides which words are read first).
+constexpr int kSatChunk = 8;
+constexpr int kSatMargin = 4;
+static_assert(kSatChunk >= 1 && kSatChunk + 2 * kSatMargin <= kSatWin, "bad window");
 constexpr int kSatBlkWords = 8;  // per block of 64 labels: N_0..N_3, R, pairs continued from HBM
 struct SatWin {
   int64_t c0, c1, w0, w1;
@@ -150,9 +162,10 @@ struct BatchDev {
   // item tables
   const uint64_t* sort_items;  int64_t n_sort;     // (set, tile, 0)
   const uint64_t* elem_items;  int64_t n_elem;     // (set, chunk of 256, 0)
-  const uint64_t* link_items;  int64_t n_link;     // (set, row tile, word tile)
+  const uint64_t* link_items;  int64_t n_link;     // (set, row tile, column tile)
   const uint64_t* pop_items;   int64_t n_pop;      // (set, bi, bj), 64-row blocks
   const uint64_t* mfma_items;  int64_t n_mfma;     // (set, BI, BJ), 256-row blocks
+  const uint64_t* mfma128_items; int64_t n_mfma128; // (set, BI, BJ), 128-row blocks
   cs_result* results;
   double c4;                                       // 4/sqrt(6), rounded once on the host
 };
@@ -161,6 +174,11 @@ hipError_t launch_batch_sprinkle(const BatchDev& b, hipStream_t st);
 hipError_t launch_batch_link(const BatchDev& b, hipStream_t st);
 hipError_t launch_batch_count_pop(const BatchDev& b, int grid, hipStream_t st);
 hipError_t launch_batch_count_mfma(const BatchDev& b, int grid, hipStream_t st);
+hipError_t launch_batch_count_mfma128(const BatchDev& b, int grid, hipStream_t st);
+// Resident workgroups per CU of a batched count kernel (kind: 1 popcount,
+// 2 matrix core with 256-row tiles, 3 with 128-row tiles).
+int batch_count_max_blocks(int kind);
+int batch_count_pop_max_blocks();
 // Once per device before the first count: kernel attributes (LDS limits).
 hipError_t init_count_mfma();
 hipError_t launch_batch_finish(const BatchDev& b, hipStream_t st);

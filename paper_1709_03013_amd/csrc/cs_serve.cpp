@@ -40,6 +40,11 @@ struct Resident {
   uint64_t* bits = nullptr;
   size_t bytes = 0;
   int users = 0;  // active requests reading it
+  // Set when the request that sprinkled and linked it has finished without
+  // error.  Until then another request must not read it: its link may still
+  // be running on the producer's stream, and a 4D matrix whose acceptance
+  // fell short is discarded and built again.
+  bool ready = false;
 };
 
 struct Request {
@@ -69,6 +74,7 @@ struct QueueState {
   std::condition_variable cv_work, cv_done;
   std::deque<std::shared_ptr<Request>> pending;
   std::unordered_map<uint64_t, std::shared_ptr<Request>> all;
+  std::deque<uint64_t> completed;  // finished, not yet returned, in completion order
   std::list<std::unique_ptr<Resident>> resident;  // most recent first
   uint64_t resident_bytes = 0;
   std::vector<Slot> slots;
@@ -127,10 +133,12 @@ static void finish_request(QueueState* q, Slot& s, cs_status st) {
     r.res.S = bd_action(r.req.d, r.req.N, r.res.n);
   }
   r.done = true;
+  q->completed.push_back(r.ticket);
   for (void* p : s.transient) q->ctx->pool.release(p);
   s.transient.clear();
   if (s.res) {
     s.res->users--;
+    if (st == CS_OK) s.res->ready = true;
     if (st != CS_OK && s.res->users == 0) {
       // a failed request's matrix is never reused
       Resident* bad = s.res;
@@ -166,6 +174,9 @@ static bool launch_request(QueueState* q, Slot& s, std::shared_ptr<Request> rq, 
   const int64_t W = row_words(N);
   const auto key = std::make_tuple(d, N, rq->req.seed);
   Resident* res = find_resident(q, key);
+  // the same matrix is still being built by an earlier request: wait for it
+  // (the caller keeps this request at the head of the queue)
+  if (res && !res->ready) return false;
   const int64_t ncand = d == 4 ? candidates_4d(N) << rq->redo : N;
   const size_t need = footprint(d, N, ncand, res == nullptr);
   if (!make_room(q, need)) return false;
@@ -301,6 +312,7 @@ static void server(QueueState* q) {
           rq->res = cs_result{};
           rq->res.status = CS_ENOMEM;
           rq->done = true;
+          q->completed.push_back(rq->ticket);
           q->outstanding--;
           q->cv_done.notify_all();
           continue;
@@ -386,6 +398,40 @@ cs_status cs_queue_poll(cs_ctx* ctx, uint64_t ticket, cs_result* out, double* ti
   if (it == q->all.end()) return fail(CS_EINVAL, "cs_queue_poll: unknown ticket %llu", (unsigned long long)ticket);
   Request& r = *it->second;
   if (!r.done) return CS_EBUSY;
+  *out = r.res;
+  if (timing) {
+    using sec = std::chrono::duration<double>;
+    timing[0] = sec(r.t_admit - r.t_submit).count();
+    timing[1] = sec(r.t_done - r.t_admit).count();
+    timing[2] = sec(r.t_done - r.t_submit).count();
+  }
+  q->all.erase(it);
+  return CS_OK;
+}
+
+cs_status cs_queue_next(cs_ctx* ctx, double timeout_s, uint64_t* ticket, cs_result* out,
+                        double* timing) {
+  if (!ctx || !ticket || !out) return fail(CS_EINVAL, "cs_queue_next: NULL argument");
+  if (!ctx->queue) return fail(CS_EINVAL, "cs_queue_next: queue not started");
+  QueueState* q = ctx->queue.get();
+  std::unique_lock<std::mutex> lk(q->mu);
+  const auto until = Clock::now() + std::chrono::duration_cast<Clock::duration>(
+                                        std::chrono::duration<double>(timeout_s > 0 ? timeout_s : 0.0));
+  for (;;) {
+    // tickets already returned by cs_queue_poll are gone from `all`
+    while (!q->completed.empty() && !q->all.count(q->completed.front())) q->completed.pop_front();
+    if (!q->completed.empty()) break;
+    if (timeout_s <= 0 || q->cv_done.wait_until(lk, until) == std::cv_status::timeout) {
+      while (!q->completed.empty() && !q->all.count(q->completed.front())) q->completed.pop_front();
+      if (q->completed.empty()) return CS_EBUSY;
+      break;
+    }
+  }
+  const uint64_t t = q->completed.front();
+  q->completed.pop_front();
+  auto it = q->all.find(t);
+  Request& r = *it->second;
+  *ticket = t;
   *out = r.res;
   if (timing) {
     using sec = std::chrono::duration<double>;

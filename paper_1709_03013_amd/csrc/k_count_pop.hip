@@ -150,10 +150,13 @@ __device__ __forceinline__ void pop_tile(const uint64_t* __restrict__ bits, int6
   }
 }
 
+// One tile per workgroup.  N_0..N_3: at least 3 waves per SIMD (the
+// accumulators and operands fit in 168 registers); the full histogram's
+// epilogue needs more registers and runs at 2.
 template <bool FULL>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_count_pop(
-    const uint64_t* __restrict__ bits, int64_t N, int64_t W, int64_t nb,
-    int kmax, uint64_t* __restrict__ rb_stats) {
+__device__ __forceinline__ void count_pop_tile(const uint64_t* __restrict__ bits, int64_t N,
+                                               int64_t W, int64_t nb, int kmax,
+                                               uint64_t* __restrict__ rb_stats) {
   __shared__ uint64_t sI[kChunk][64];
   __shared__ uint64_t sJ[kChunk][64];
   extern __shared__ uint32_t lds_hist[];  // FULL only: min(kmax+1, kLdsBins) bins
@@ -166,9 +169,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
   pop_tile<FULL>(bits, N, W, bi, bj, kmax, rb_stats, lds_hist, sI, sJ);
 }
 
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_count_pop(
+    const uint64_t* __restrict__ bits, int64_t N, int64_t W, int64_t nb,
+    int kmax, uint64_t* __restrict__ rb_stats) {
+  count_pop_tile<false>(bits, N, W, nb, kmax, rb_stats);
+}
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_count_pop_full(
+    const uint64_t* __restrict__ bits, int64_t N, int64_t W, int64_t nb,
+    int kmax, uint64_t* __restrict__ rb_stats) {
+  count_pop_tile<true>(bits, N, W, nb, kmax, rb_stats);
+}
+
 // Batched, persistent: each 64-lane workgroup takes (set, bi, bj) items,
-// sorted longest first, in snake order until none is left.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_batch_count_pop(
+// sorted longest first, in snake order until none is left.  The item loop
+// and the set table need registers beyond the single-tile kernel's 168.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_batch_count_pop(
     BatchDev b) {
   __shared__ uint64_t sI[kChunk][64];
   __shared__ uint64_t sJ[kChunk][64];
@@ -248,11 +264,11 @@ hipError_t launch_count_pop(const uint64_t* bits, int64_t N, int64_t W,
   const int64_t ntiles = nb * (nb + 1) / 2;
   if (ntiles > 0x7fffffffLL) return hipErrorInvalidValue;
   if (kmax <= 3) {
-    hipLaunchKernelGGL(k_count_pop<false>, dim3((unsigned)ntiles), dim3(64), 0, st,
+    hipLaunchKernelGGL(k_count_pop, dim3((unsigned)ntiles), dim3(64), 0, st,
                        bits, N, W, nb, kmax, rb_stats);
   } else {
     const size_t lds = (size_t)(kmax + 1 < kLdsBins ? kmax + 1 : kLdsBins) * sizeof(uint32_t);
-    hipLaunchKernelGGL(k_count_pop<true>, dim3((unsigned)ntiles), dim3(64), lds, st,
+    hipLaunchKernelGGL(k_count_pop_full, dim3((unsigned)ntiles), dim3(64), lds, st,
                        bits, N, W, nb, kmax, rb_stats);
   }
   return hipGetLastError();
@@ -262,6 +278,12 @@ hipError_t launch_batch_count_pop(const BatchDev& b, int grid, hipStream_t st) {
   if (b.n_pop <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_batch_count_pop, dim3((unsigned)grid), dim3(64), 0, st, b);
   return hipGetLastError();
+}
+
+int batch_count_pop_max_blocks() {
+  int n = 0;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_batch_count_pop, 64, 0);
+  return e == hipSuccess && n > 0 ? n : 1;
 }
 
 hipError_t launch_batch_finish(const BatchDev& b, hipStream_t st) {

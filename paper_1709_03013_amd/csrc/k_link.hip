@@ -1,18 +1,34 @@
 // k_link.hip -- the O(N^2) linking step (Sec. 2.2): the packed, symmetric,
 // zero-diagonal causal matrix from time-sorted coordinates.
 //
-// gfx950 design: a wave's 64 lanes are 64 consecutive columns k of a 64-bit
-// word (four words per pass: columns k, k+64, k+128, k+192 per lane); for
-// each row i (wave-uniform, coordinates broadcast from LDS) the relation
-// tests produce each word directly as the wave's compare mask, written into
-// lane i%64 with v_writelane (one M0 lane select per row for the four
-// words).  After 64 rows every lane holds its row's words of a 64x64-word
-// tile, which is staged in LDS and stored row by row with fully coalesced
-// 512-byte rows.
+// gfx950 design.  Each pair is tested once.  The matrix is cut into blocks
+// of 64 x 64 labels; block (I, K) with I < K (rows of block I, columns of
+// block K) is tested as 64 wave-wide compares: the 64 lanes are the columns
+// k, the rows i = 64I + r come one at a time as wave-uniform coordinates
+// (scalar loads), and each compare yields the lane mask of the columns
+// related to row i.  That mask is shifted into every lane's own 32-bit
+// accumulator by one carry-in add (acc = acc + acc + carry), so after the 64
+// rows lane k holds the 64 relation bits of column k against the rows of
+// block I: word I of row k, the lower-triangle word.  An in-register 64x64
+// bit transpose (permlane / DPP / swizzle exchanges, one bit-field insert
+// per step) turns it into word K of the rows of block I, the upper-triangle
+// word.  So a block costs 64 compare steps (2 compares in 2D, the 4D and de
+// Sitter tests in binary64) plus 64 carry-in adds and one transpose for
+// 4096 pairs, and writes both of its mirror words.
 //
-// Relation (Sec. 1.1, strict timelike separation), for either order of the
-// pair, so the symmetric matrix needs no index test:
-//   2D: (u_i < u_k and v_i < v_k) or (u_k < u_i and v_k < v_i);
+// A workgroup of 4 waves owns a tile of 8 x 8 blocks (512 x 512 labels) of
+// the upper triangle (row tile <= column tile); wave w takes the column
+// blocks 2w and 2w+1 and runs their compares interleaved.  Upper-triangle
+// words are collected in LDS and leave as 64-byte row segments (8 words of
+// each of the tile's 512 rows); lower-triangle words stay in the lane that
+// owns the row and leave as 64-byte segments too.  Diagonal tiles assemble
+// all three kinds (upper, lower, diagonal block) in LDS.  Padding words
+// (columns past N up to the row stride) are written as zeros.
+//
+// Relation (Sec. 1.1, strict timelike separation):
+//   2D: u_i < u_k and v_i < v_k for i earlier (off-diagonal blocks: labels
+//       are time-sorted, so only that order can hold); both orders inside a
+//       diagonal block;
 //   4D: dt*dt > (dx*dx + dy*dy) + dz*dz with d* = coordinate of k minus
 //       coordinate of i.  Rounding is sign-symmetric, so this equals the
 //       test written with the earlier element subtracted; dt*dt > 0 implies
@@ -20,11 +36,10 @@
 //   de Sitter slab (Sec. 6.1), rows (w = tan eta, x, y) with (x, y) an
 //       unnormalised direction: |d eta| > geodesic angle, which for eta0 <
 //       pi/4 reads dot > 0 and |w_i - w_k| * dot > |cross| * (1 + w_i w_k)
-//       (tangent of a difference).  Every operand is exactly symmetric in the
-//       pair (products commute, a - b = -(b - a)).
-// No fused multiply-add anywhere.
-#include <cstdlib>
-
+//       (tangent of a difference).  Every operand is exactly symmetric in
+//       the pair (products commute, a - b = -(b - a)).
+// No fused multiply-add anywhere.  An element is never related to itself
+// (every test is strict), so the diagonal needs no mask.
 #include "cs_internal.h"
 
 #pragma clang fp contract(off)
@@ -32,24 +47,24 @@
 namespace cs {
 namespace {
 
+constexpr int kLT = 8;            // blocks per tile side
+constexpr int kRowPad = kLT + 1;  // LDS words per staged row: odd, so 8-byte accesses spread banks
+
 template <int D>
 struct Pt {
   double c[D];
 };
 
 // Relation of a (the row, wave-uniform) to b (this lane's column) over the
-// wave, as a 64-bit lane mask (Sec. 1.1, strict).  DIR: 0 = either order
-// (the diagonal 64x64 block), 1 = a before b (columns after the rows), 2 = b
-// before a.  Each comparison goes straight to a lane mask (no booleans in
-// VGPRs) and the masks are combined with scalar ANDs.
-template <int D, int DIR>
+// wave as a 64-bit lane mask.  SYM: either order (a diagonal block);
+// otherwise a is the earlier element.  Each compare goes straight to a lane
+// mask (no booleans in VGPRs); the masks combine with scalar ANDs.
+template <int D, bool SYM>
 __device__ __forceinline__ uint64_t related_mask(const Pt<D>& a, const Pt<D>& b) {
   if constexpr (D == 2) {
     const uint64_t fwd = __ballot(a.c[0] < b.c[0]) & __ballot(a.c[1] < b.c[1]);
-    if constexpr (DIR == 1) return fwd;
-    const uint64_t bwd = __ballot(b.c[0] < a.c[0]) & __ballot(b.c[1] < a.c[1]);
-    if constexpr (DIR == 2) return bwd;
-    return fwd | bwd;
+    if constexpr (!SYM) return fwd;
+    return fwd | (__ballot(b.c[0] < a.c[0]) & __ballot(b.c[1] < a.c[1]));
   } else if constexpr (D == 3) {
     const double dot = a.c[1] * b.c[1] + a.c[2] * b.c[2];
     const double cr = fabs(a.c[1] * b.c[2] - a.c[2] * b.c[1]);
@@ -67,220 +82,358 @@ __device__ __forceinline__ uint64_t related_mask(const Pt<D>& a, const Pt<D>& b)
   }
 }
 
-// 64 relation words of one column word: lane r ends with word (i0 + r, w).
-// The row's coordinates are LDS broadcasts; each row's word is the wave's
-// compare mask, written into lane r with v_writelane.
-template <int D, int DIR, bool PARTIAL>
-__device__ __forceinline__ uint64_t link_word(const double (*rowc)[64], const Pt<D>& pk,
-                                              uint64_t kmask) {
-  int lo = 0, hi = 0;
-#pragma unroll 8
-  for (int r = 0; r < 64; ++r) {
-    Pt<D> pi;
-#pragma unroll
-    for (int q = 0; q < D; ++q) pi.c[q] = rowc[q][r];
-    const uint64_t rel = related_mask<D, DIR>(pi, pk);
-    const uint64_t m = PARTIAL ? (kmask & rel) : rel;
-    const int mlo = (int)(uint32_t)m, mhi = (int)(uint32_t)(m >> 32);
-    // the lane select goes through M0 (one SGPR operand per VOP3 on gfx9);
-    // hipcc warns that M0 is reserved: the link kernels' own code keeps no
-    // value in M0 (their only M0 writes are these statements)
-    asm("s_mov_b32 m0, %4\n\tv_writelane_b32 %0, %2, m0\n\tv_writelane_b32 %1, %3, m0"
-        : "+v"(lo), "+v"(hi)
-        : "s"(mlo), "s"(mhi), "s"(r)
-        : "m0");
-  }
-  return (uint64_t)(uint32_t)lo | ((uint64_t)(uint32_t)hi << 32);
+// acc * 2 + (this lane's bit of m): one carry-in add shifts the lane mask
+// of the newest row into every lane's accumulator.
+__device__ __forceinline__ uint32_t shift_in(uint32_t acc, uint64_t m) {
+  uint32_t r;
+  uint64_t carry_out;
+  asm("v_addc_co_u32 %0, %1, %2, %2, %3" : "=v"(r), "=s"(carry_out) : "v"(acc), "s"(m));
+  return r;
 }
 
-// The same for two column words at once (this lane's columns k and k + 64):
-// one LDS broadcast and one lane select per row serve both.
-template <int D, int DIR, bool PARTIAL>
-__device__ __forceinline__ void link_word2(const double (*rowc)[64], const Pt<D>& pk0,
-                                           const Pt<D>& pk1, uint64_t kmask0, uint64_t kmask1,
-                                           uint64_t* my0, uint64_t* my1) {
-  int lo0 = 0, hi0 = 0, lo1 = 0, hi1 = 0;
-#pragma unroll 4
-  for (int r = 0; r < 64; ++r) {
-    Pt<D> pi;
-#pragma unroll
-    for (int q = 0; q < D; ++q) pi.c[q] = rowc[q][r];
-    const uint64_t r0 = related_mask<D, DIR>(pi, pk0), r1 = related_mask<D, DIR>(pi, pk1);
-    const uint64_t m0 = PARTIAL ? (kmask0 & r0) : r0;
-    const uint64_t m1 = PARTIAL ? (kmask1 & r1) : r1;
-    asm("s_mov_b32 m0, %8\n\tv_writelane_b32 %0, %4, m0\n\tv_writelane_b32 %1, %5, m0\n\t"
-        "v_writelane_b32 %2, %6, m0\n\tv_writelane_b32 %3, %7, m0"
-        : "+v"(lo0), "+v"(hi0), "+v"(lo1), "+v"(hi1)
-        : "s"((int)(uint32_t)m0), "s"((int)(uint32_t)(m0 >> 32)), "s"((int)(uint32_t)m1),
-          "s"((int)(uint32_t)(m1 >> 32)), "s"(r)
-        : "m0");
-  }
-  *my0 = (uint64_t)(uint32_t)lo0 | ((uint64_t)(uint32_t)hi0 << 32);
-  *my1 = (uint64_t)(uint32_t)lo1 | ((uint64_t)(uint32_t)hi1 << 32);
+// Lane exchange with lane ^ J inside a 32-bit step of the transpose.
+template <int J>
+__device__ __forceinline__ uint32_t xchg(uint32_t x) {
+  if constexpr (J == 16)
+    return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, (16 << 10) | 0x1F);  // xor 16 in 32
+  else if constexpr (J == 8)
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x128, 0xF, 0xF, true);  // row_ror:8
+  else if constexpr (J == 4)
+    return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, (4 << 10) | 0x1F);  // xor 4 in 32
+  else if constexpr (J == 2)
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, true);  // quad 2,3,0,1
+  else
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, true);  // quad 1,0,3,2
 }
 
-// Four column words at once (columns k + 64u, u = 0..3).
-template <int D, int DIR, bool PARTIAL>
-__device__ __forceinline__ void link_word4(const double (*rowc)[64], const Pt<D> (&pk)[4],
-                                           const uint64_t (&km)[4], uint64_t (&my)[4]) {
-  int lo0 = 0, hi0 = 0, lo1 = 0, hi1 = 0, lo2 = 0, hi2 = 0, lo3 = 0, hi3 = 0;
+// (keep & x) | (~keep & y) in one instruction.
+__device__ __forceinline__ uint32_t bfi(uint32_t keep, uint32_t x, uint32_t y) {
+  uint32_t r;
+  asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(keep), "v"(x), "v"(y));
+  return r;
+}
+
+// Per-lane constants of the 32-bit transpose steps.  Step J pairs lane bit J
+// with bit-index bit J: a lane whose bit J is clear keeps its bits whose
+// index has bit J clear and takes its partner's such bits moved up by J; a
+// lane whose bit J is set keeps the others and takes the partner's moved
+// down by J.  J = 16 and 8 move whole bytes (one byte permute of the word
+// and its partner's); J = 4, 2, 1 rotate the partner's word (the bits a
+// rotate wraps around land where the lane keeps its own) and insert.
+struct TConsts {
+  uint32_t sel16, sel8;
+  uint32_t keep4, rot4, keep2, rot2, keep1, rot1;
+};
+
+__device__ __forceinline__ TConsts tconsts(int lane) {
+  TConsts t;
+  // byte selectors of v_perm (partner's bytes 4-7, own bytes 0-3)
+  t.sel16 = (lane & 16) ? 0x03020706u : 0x05040100u;
+  t.sel8 = (lane & 8) ? 0x03070105u : 0x06020400u;
+  t.keep4 = (lane & 4) ? 0xF0F0F0F0u : 0x0F0F0F0Fu;
+  t.rot4 = (lane & 4) ? 4u : 28u;
+  t.keep2 = (lane & 2) ? 0xCCCCCCCCu : 0x33333333u;
+  t.rot2 = (lane & 2) ? 2u : 30u;
+  t.keep1 = (lane & 1) ? 0xAAAAAAAAu : 0x55555555u;
+  t.rot1 = (lane & 1) ? 1u : 31u;
+  return t;
+}
+
+template <int J>
+__device__ __forceinline__ uint32_t tbits(uint32_t x, uint32_t keep, uint32_t rot) {
+  const uint32_t p = xchg<J>(x);
+  return bfi(keep, x, __builtin_amdgcn_alignbit(p, p, rot));
+}
+
+// 64x64 bit transpose across the wave: lane k's bit b moves to lane b's
+// bit k.  First the two 32x32 off-diagonal quarters trade places (lanes
+// 32-63 of the low words with lanes 0-31 of the high words, one permlane
+// swap), then the 32x32 transposes run on both halves at once.
+__device__ __forceinline__ uint64_t transpose64(uint64_t w, const TConsts& t) {
+  const auto q = __builtin_amdgcn_permlane32_swap((uint32_t)w, (uint32_t)(w >> 32), false, false);
+  uint32_t lo = q[0], hi = q[1];
+  lo = __builtin_amdgcn_perm(xchg<16>(lo), lo, t.sel16);
+  hi = __builtin_amdgcn_perm(xchg<16>(hi), hi, t.sel16);
+  lo = __builtin_amdgcn_perm(xchg<8>(lo), lo, t.sel8);
+  hi = __builtin_amdgcn_perm(xchg<8>(hi), hi, t.sel8);
+  lo = tbits<4>(lo, t.keep4, t.rot4);
+  hi = tbits<4>(hi, t.keep4, t.rot4);
+  lo = tbits<2>(lo, t.keep2, t.rot2);
+  hi = tbits<2>(hi, t.keep2, t.rot2);
+  lo = tbits<1>(lo, t.keep1, t.rot1);
+  hi = tbits<1>(hi, t.keep1, t.rot1);
+  return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// Coordinates of label i (clamped to the last element; callers mask).
+template <int D>
+__device__ __forceinline__ Pt<D> point(const double* __restrict__ coords, int64_t N, int64_t i) {
+  Pt<D> p;
+  const int64_t j = i < N ? i : N - 1;
+#pragma unroll
+  for (int q = 0; q < D; ++q) p.c[q] = coords[(int64_t)q * N + j];
+  return p;
+}
+
+// Two column blocks against one earlier row block I (all 64 rows exist):
+// lane k gets word I of rows 64K0 + k and 64K1 + k (columns past N are
+// cleared by the caller).  Rows arrive in groups of four (scalar loads of
+// each coordinate), the next group loaded while the current one is
+// compared; a group's eight compare masks are formed before any is shifted
+// in, so the compare -> AND -> add chains of different rows overlap.
+template <int D>
+__device__ __forceinline__ void block_pair(const double* __restrict__ coords, int64_t N, int64_t I,
+                                           const Pt<D>& p0, const Pt<D>& p1, uint64_t* w0,
+                                           uint64_t* w1) {
+  constexpr int G = 4;
+  const double* rc[D];
+#pragma unroll
+  for (int q = 0; q < D; ++q) rc[q] = coords + (int64_t)q * N + I * 64;
+  auto load = [&](int r0, Pt<D> (&g)[G]) {
+#pragma unroll
+    for (int j = 0; j < G; ++j)
+#pragma unroll
+      for (int q = 0; q < D; ++q) g[j].c[q] = rc[q][r0 - j];
+  };
+  // One group: the eight compare masks, then the next group's coordinates
+  // into the same registers (r_next < 0: none), then the eight carry-in adds
+  // while those loads are in flight.
+  auto step = [&](Pt<D> (&g)[G], int r_next, uint32_t& a0, uint32_t& a1) {
+    uint64_t m0[G], m1[G];
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      m0[j] = related_mask<D, false>(g[j], p0);
+      m1[j] = related_mask<D, false>(g[j], p1);
+    }
+    if (r_next >= 0) load(r_next, g);
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      a0 = shift_in(a0, m0[j]);
+      a1 = shift_in(a1, m1[j]);
+    }
+  };
+  uint32_t h0 = 0, h1 = 0, l0 = 0, l1 = 0;
+  Pt<D> cur[G];
+  load(63, cur);
 #pragma unroll 2
-  for (int r = 0; r < 64; ++r) {
-    Pt<D> pi;
-#pragma unroll
-    for (int q = 0; q < D; ++q) pi.c[q] = rowc[q][r];
-    uint64_t m[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const uint64_t rel = related_mask<D, DIR>(pi, pk[u]);
-      m[u] = PARTIAL ? (km[u] & rel) : rel;
-    }
-    asm("s_mov_b32 m0, %16\n\t"
-        "v_writelane_b32 %0, %8, m0\n\tv_writelane_b32 %1, %9, m0\n\t"
-        "v_writelane_b32 %2, %10, m0\n\tv_writelane_b32 %3, %11, m0\n\t"
-        "v_writelane_b32 %4, %12, m0\n\tv_writelane_b32 %5, %13, m0\n\t"
-        "v_writelane_b32 %6, %14, m0\n\tv_writelane_b32 %7, %15, m0"
-        : "+v"(lo0), "+v"(hi0), "+v"(lo1), "+v"(hi1), "+v"(lo2), "+v"(hi2), "+v"(lo3), "+v"(hi3)
-        : "s"((int)(uint32_t)m[0]), "s"((int)(uint32_t)(m[0] >> 32)), "s"((int)(uint32_t)m[1]),
-          "s"((int)(uint32_t)(m[1] >> 32)), "s"((int)(uint32_t)m[2]), "s"((int)(uint32_t)(m[2] >> 32)),
-          "s"((int)(uint32_t)m[3]), "s"((int)(uint32_t)(m[3] >> 32)), "s"(r)
-        : "m0");
-  }
-  my[0] = (uint64_t)(uint32_t)lo0 | ((uint64_t)(uint32_t)hi0 << 32);
-  my[1] = (uint64_t)(uint32_t)lo1 | ((uint64_t)(uint32_t)hi1 << 32);
-  my[2] = (uint64_t)(uint32_t)lo2 | ((uint64_t)(uint32_t)hi2 << 32);
-  my[3] = (uint64_t)(uint32_t)lo3 | ((uint64_t)(uint32_t)hi3 << 32);
+  for (int g = 0; g < 32 / G; ++g)  // rows 63..32: the high words
+    step(cur, 63 - G * (g + 1), h0, h1);
+#pragma unroll 2
+  for (int g = 0; g < 32 / G; ++g)  // rows 31..0: the low words
+    step(cur, g + 1 < 32 / G ? 31 - G * (g + 1) : -1, l0, l1);
+  *w0 = (uint64_t)l0 | ((uint64_t)h0 << 32);
+  *w1 = (uint64_t)l1 | ((uint64_t)h1 << 32);
 }
 
-// One 64-row x 64-word tile of the matrix, rows i0.., words w0.. (256 threads).
-// The 64 rows' coordinates are staged in LDS and read as broadcasts; each
-// wave builds 16 words, one column word (64 columns, one per lane) at a time,
-// and the tile leaves through LDS as coalesced 512-byte row segments.  Off
-// the diagonal block only one order of each pair can hold (labels are
-// time-sorted), so only that direction is tested.
-template <int D, int NW = 1>
+// One column block against row block I <= K: lane k gets word I of row
+// 64K + k.  SYM for the diagonal block.  Rows past N contribute no bits.
+template <int D, bool SYM>
+__device__ __forceinline__ uint64_t block_one(const double* __restrict__ coords, int64_t N, int64_t I,
+                                              const Pt<D>& p, uint64_t km) {
+  uint32_t h = 0, l = 0;
+  const int64_t nrows = N - I * 64;  // rows of block I that exist (>= 1)
+  for (int r = 63; r >= 0; --r) {
+    const Pt<D> a = point<D>(coords, N, I * 64 + r);
+    const uint64_t m = r < nrows ? (related_mask<D, SYM>(a, p) & km) : 0ull;
+    if (r >= 32)
+      h = shift_in(h, m);
+    else
+      l = shift_in(l, m);
+  }
+  return (uint64_t)l | ((uint64_t)h << 32);
+}
+
+// Tiles of R row blocks x kLT column blocks (R divides kLT).  Row tile ti
+// holds row blocks R*ti .. R*ti+R-1; column tile tk holds column blocks (and
+// words) kLT*tk .. kLT*tk+kLT-1.  Only column tiles that reach the diagonal
+// or beyond are needed: tk >= floor(R*ti / kLT).
+template <int R>
+__host__ __device__ inline int64_t first_col_tile(int64_t ti) {
+  return (R * ti) / kLT;
+}
+
+// Tiles in row tiles 0..T-1: T*nct - sum_{t<T} floor(t/q), q = kLT/R.
+template <int R>
+__host__ __device__ inline int64_t tiles_before(int64_t T, int64_t nct) {
+  constexpr int64_t q = kLT / R;
+  const int64_t a = T / q, b = T % q;
+  return T * nct - (q * a * (a - 1) / 2 + a * b);
+}
+
+template <int R>
+__device__ __forceinline__ void tile_of(int64_t id, int64_t nrt, int64_t nct, int64_t* ti,
+                                        int64_t* tk) {
+  int64_t lo = 0, hi = nrt - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (tiles_before<R>(mid, nct) <= id)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  *ti = lo;
+  *tk = first_col_tile<R>(lo) + (id - tiles_before<R>(lo, nct));
+}
+
+// LDS staging of a tile's words (one raw array, views per R):
+//  up:  the rows of min(R, 4) row blocks x kLT words of the column tile, row
+//       stride kRowPad (odd, so 64 lanes writing one word of 64 rows spread
+//       over the banks); flushed every min(R, 4) row blocks;
+//  low: the 512 rows of the column tile x R words of the row tile, word w of
+//       row r at w ^ ((r >> 1) & (R - 1)).
+template <int R>
+constexpr int up_words() {
+  return (R < 4 ? R : 4) * 64 * kRowPad;
+}
+template <int R>
+constexpr int stage_words() {
+  return up_words<R>() + kLT * 64 * R;
+}
+
+template <int R>
+__device__ __forceinline__ int lpos(int r, int w) {
+  return r * R + (w ^ ((r >> 1) & (R - 1)));
+}
+
+// The tile (ti, tk) by one 256-thread workgroup.  Wave w owns column blocks
+// 2w and 2w+1 of the tile.  For a row block I and a column block K of the
+// tile: I < K, the block is tested and gives the lower-triangle words (rows
+// of K, word I: low) and, transposed, the upper-triangle words (rows of I,
+// word K: up); I == K, the diagonal block gives its own words (up); I > K
+// belongs to another tile (as its K < I pair).  Columns past the last
+// element up to the row stride are written as zero words (up).  A flush
+// skips staged words the tile did not produce (only in tiles that cross
+// the diagonal).
+template <int D, int R>
 __device__ __forceinline__ void link_tile(const double* __restrict__ coords, int64_t N,
-                                          uint64_t* __restrict__ bits, int64_t W,
-                                          int64_t i0, int64_t w0,
-                                          uint64_t (*tile)[65], double (*rowc)[64]) {
+                                          uint64_t* __restrict__ bits, int64_t W, int64_t ti,
+                                          int64_t tk, uint64_t* st) {
+  constexpr int UR = R < 4 ? R : 4;  // row blocks per up flush
+  uint64_t* up = st;
+  uint64_t* low = st + up_words<R>();
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  if (threadIdx.x < 64) {
-    const int64_t i = i0 + lane;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t NB = (N + 63) >> 6;  // blocks that hold elements
+  const int64_t I0 = R * ti, K0 = kLT * tk;
+  const bool crosses = K0 < I0 + R;  // some column block at or before some row block
+  const TConsts tc = tconsts(lane);
+
+  int kl[2];
+  int64_t K[2];
+  bool live[2];
+  Pt<D> p[2];
+  uint64_t km[2], kv[2];
 #pragma unroll
-    for (int q = 0; q < D; ++q) rowc[q][lane] = i < N ? coords[(int64_t)q * N + i] : 0.0;
+  for (int c = 0; c < 2; ++c) {
+    kl[c] = 2 * wave + c;
+    K[c] = K0 + kl[c];
+    live[c] = K[c] < NB;
+    const int64_t k = K[c] * 64 + lane;
+    km[c] = __ballot(k < N);
+    kv[c] = k < N ? ~0ull : 0ull;
+    p[c] = point<D>(coords, N, live[c] ? k : 0);
   }
-  __syncthreads();
-  if constexpr (NW == 4) {
-    for (int wl = 0; wl < 16; wl += 4) {
-      const int wloc = wave * 16 + wl;
-      const int64_t w = w0 + wloc;  // words w .. w + 3
-      uint64_t my[4] = {0, 0, 0, 0};
-      if (w < W) {  // W is a multiple of 4 and w of 4, so w + 3 < W too
-        Pt<D> pk[4];
-        uint64_t km[4];
+  auto put_up = [&](int il, int c, uint64_t w) { up[((il % UR) * 64 + lane) * kRowPad + kl[c]] = w; };
+  auto put_low = [&](int il, int c, uint64_t w) { low[lpos<R>(kl[c] * 64 + lane, il)] = w; };
+
+  for (int il = 0; il < R; ++il) {
+    const int64_t I = I0 + il;
+    if (I < NB) {
+      const bool off0 = live[0] && I < K[0], off1 = live[1] && I < K[1];
+      if (off0 && off1) {
+        uint64_t w0, w1;
+        block_pair<D>(coords, N, I, p[0], p[1], &w0, &w1);
+        w0 &= kv[0];
+        w1 &= kv[1];
+        put_low(il, 0, w0);
+        put_low(il, 1, w1);
+        put_up(il, 0, transpose64(w0, tc));
+        put_up(il, 1, transpose64(w1, tc));
+      } else {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int64_t k = (w + u) * 64 + lane;
-          km[u] = __ballot(k < N);
-#pragma unroll
-          for (int q = 0; q < D; ++q) pk[u].c[q] = coords[(int64_t)q * N + (k < N ? k : 0)];
+        for (int c = 0; c < 2; ++c) {
+          if (live[c] && I == K[c]) {
+            put_up(il, c, block_one<D, true>(coords, N, I, p[c], km[c]));
+          } else if (live[c] && I < K[c]) {
+            const uint64_t w = block_one<D, false>(coords, N, I, p[c], km[c]);
+            put_low(il, c, w);
+            put_up(il, c, transpose64(w, tc));
+          }
         }
-        if (km[3] != ~0ull)  // a column past N: the last words only
-          link_word4<D, 0, true>(rowc, pk, km, my);
-        else if (w * 64 >= i0 + 64)
-          link_word4<D, 1, false>(rowc, pk, km, my);
-        else if (w * 64 + 256 <= i0)
-          link_word4<D, 2, false>(rowc, pk, km, my);
-        else
-          link_word4<D, 0, false>(rowc, pk, km, my);
       }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) tile[lane][wloc + u] = my[u];
     }
-  } else if constexpr (NW == 2) {
-    for (int wl = 0; wl < 16; wl += 2) {
-      const int wloc = wave * 16 + wl;
-      const int64_t w = w0 + wloc;  // words w and w + 1
-      uint64_t my0 = 0, my1 = 0;
-      if (w < W) {  // W is a multiple of 4, so w + 1 < W too
-        const int64_t k0 = w * 64 + lane, k1 = k0 + 64;
-        const uint64_t km0 = __ballot(k0 < N), km1 = __ballot(k1 < N);
-        Pt<D> p0, p1;
 #pragma unroll
-        for (int q = 0; q < D; ++q) {
-          p0.c[q] = coords[(int64_t)q * N + (k0 < N ? k0 : 0)];
-          p1.c[q] = coords[(int64_t)q * N + (k1 < N ? k1 : 0)];
-        }
-        if (km1 != ~0ull)  // a column past N: the last words only
-          link_word2<D, 0, true>(rowc, p0, p1, km0, km1, &my0, &my1);
-        else if (w * 64 >= i0 + 64)
-          link_word2<D, 1, false>(rowc, p0, p1, km0, km1, &my0, &my1);
-        else if (w * 64 + 128 <= i0)
-          link_word2<D, 2, false>(rowc, p0, p1, km0, km1, &my0, &my1);
-        else
-          link_word2<D, 0, false>(rowc, p0, p1, km0, km1, &my0, &my1);
+    for (int c = 0; c < 2; ++c)
+      if (!live[c] && K[c] < W) put_up(il, c, 0ull);
+    if (il % UR == UR - 1) {
+      // rows of row blocks I0+il-UR+1 .. I0+il, words K0 .. K0+7, 16 bytes
+      // per lane (W is a multiple of 4: a pair never straddles the row end)
+      __syncthreads();
+      const int64_t b0 = I0 + il - (UR - 1);
+      for (int t = threadIdx.x; t < UR * 64 * 4; t += 256) {
+        const int r = t >> 2, q = t & 3;
+        const int64_t row = b0 * 64 + r, w = K0 + 2 * q;
+        if (row >= N || w >= W) continue;
+        // words before the row's own block belong to lower-triangle words
+        // written elsewhere (only where the tile crosses the diagonal)
+        const int64_t first = crosses ? (row >> 6) : 0;
+        const uint64_t x = up[r * kRowPad + 2 * q], y = up[r * kRowPad + 2 * q + 1];
+        if (w >= first)
+          *(uint4*)(bits + row * W + w) =
+              make_uint4((uint32_t)x, (uint32_t)(x >> 32), (uint32_t)y, (uint32_t)(y >> 32));
+        else if (w + 1 == first)
+          bits[row * W + w + 1] = y;
       }
-      tile[lane][wloc] = my0;
-      tile[lane][wloc + 1] = my1;
-    }
-  } else {
-    for (int wl = 0; wl < 16; ++wl) {
-      const int wloc = wave * 16 + wl;
-      const int64_t w = w0 + wloc;
-      uint64_t my = 0;
-      if (w < W) {
-        const int64_t k = w * 64 + lane;
-        const bool kval = k < N;
-        const uint64_t kmask = __ballot(kval);
-        const int64_t kk = kval ? k : 0;
-        Pt<D> pk;
-#pragma unroll
-        for (int q = 0; q < D; ++q) pk.c[q] = coords[(int64_t)q * N + kk];
-        if (kmask != ~0ull)  // a column past N: the last word only
-          my = link_word<D, 0, true>(rowc, pk, kmask);
-        else if (w * 64 >= i0 + 64)
-          my = link_word<D, 1, false>(rowc, pk, kmask);
-        else if (w * 64 + 64 <= i0)
-          my = link_word<D, 2, false>(rowc, pk, kmask);
-        else
-          my = link_word<D, 0, false>(rowc, pk, kmask);
-      }
-      tile[lane][wloc] = my;
+      __syncthreads();
     }
   }
+  // low: rows of the column tile, words I0 .. I0+R-1 of the row blocks
+  // before them
   __syncthreads();
-  for (int p = 0; p < 16; ++p) {
-    const int r = p * 4 + wave;
-    const int64_t i = i0 + r;
-    const int64_t w = w0 + lane;
-    if (i < N && w < W) bits[i * W + w] = tile[r][lane];
+  constexpr int PW = R >= 2 ? 2 : 1;  // words per lane
+  constexpr int LPR = R / PW;         // lanes per row
+  for (int t = threadIdx.x; t < kLT * 64 * LPR; t += 256) {
+    const int r = t / LPR, q = t % LPR;
+    const int64_t row = K0 * 64 + r, w = I0 + PW * q;
+    const int64_t rb = row >> 6;
+    if (row >= N) continue;
+    if constexpr (PW == 2) {
+      const uint64_t x = low[lpos<R>(r, PW * q)], y = low[lpos<R>(r, PW * q + 1)];
+      if (w + 1 < rb) {
+        *(uint4*)(bits + row * W + w) =
+            make_uint4((uint32_t)x, (uint32_t)(x >> 32), (uint32_t)y, (uint32_t)(y >> 32));
+      } else if (w < rb) {
+        bits[row * W + w] = x;
+      }
+    } else {
+      if (w < rb) bits[row * W + w] = low[lpos<R>(r, 0)];
+    }
   }
 }
 
-template <int D, int NW>
-__global__ __launch_bounds__(256) void k_link(const double* __restrict__ coords,
-                                              int64_t N,
-                                              uint64_t* __restrict__ bits,
-                                              int64_t W) {
-  __shared__ uint64_t tile[64][65];
-  __shared__ double rowc[D][64];
-  link_tile<D, NW>(coords, N, bits, W, (int64_t)blockIdx.y * 64, (int64_t)blockIdx.x * 64, tile, rowc);
+template <int D, int R>
+__global__ __launch_bounds__(256) void k_link(const double* __restrict__ coords, int64_t N,
+                                              uint64_t* __restrict__ bits, int64_t W,
+                                              int64_t nrt, int64_t nct) {
+  __shared__ uint64_t stage[stage_words<R>()];
+  int64_t ti, tk;
+  tile_of<R>((int64_t)blockIdx.x, nrt, nct, &ti, &tk);
+  link_tile<D, R>(coords, N, bits, W, ti, tk, stage);
 }
 
-// Batched: one workgroup per (set, 64-row tile, 64-word tile) item.
+// Batched: one workgroup per (set, row tile, column tile) item, tiles of
+// kBatchR row blocks.
+constexpr int kBatchR = 4;
+
 __global__ __launch_bounds__(256) void k_batch_link(BatchDev b) {
-  __shared__ uint64_t tile[64][65];
-  __shared__ double rowc[4][64];
-  int64_t set, ti, tw;
-  unpack_item(b.link_items[blockIdx.x], &set, &ti, &tw);
+  __shared__ uint64_t stage[stage_words<kBatchR>()];
+  int64_t set, ti, tk;
+  unpack_item(b.link_items[blockIdx.x], &set, &ti, &tk);
   const BatchSet bs = b.sets[set];
   if (bs.d == 2)
-    link_tile<2, 4>(b.coords + bs.coords_off, bs.N, b.bits + bs.bits_off, bs.W, ti * 64, tw * 64,
-                    tile, rowc);
+    link_tile<2, kBatchR>(b.coords + bs.coords_off, bs.N, b.bits + bs.bits_off, bs.W, ti, tk, stage);
   else
-    link_tile<4, 4>(b.coords + bs.coords_off, bs.N, b.bits + bs.bits_off, bs.W, ti * 64, tw * 64,
-                    tile, rowc);
+    link_tile<4, kBatchR>(b.coords + bs.coords_off, bs.N, b.bits + bs.bits_off, bs.W, ti, tk, stage);
 }
 
 __global__ __launch_bounds__(256) void k_fill_u64(uint64_t* __restrict__ p,
@@ -318,37 +471,50 @@ __global__ __launch_bounds__(256) void k_validate(const uint64_t* __restrict__ b
 
 }  // namespace
 
+namespace {
+template <int R>
+int64_t tile_count(int64_t N, int64_t W) {
+  const int64_t nb = (N + 63) / 64;
+  return tiles_before<R>((nb + R - 1) / R, (W + kLT - 1) / kLT);
+}
+
+template <int D, int R>
+hipError_t launch_r(int64_t N, const double* coords, uint64_t* bits, int64_t W, hipStream_t st) {
+  const int64_t nb = (N + 63) / 64;
+  const int64_t nrt = (nb + R - 1) / R, nct = (W + kLT - 1) / kLT;
+  const int64_t tiles = tiles_before<R>(nrt, nct);
+  if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_link<D, R>), dim3((unsigned)tiles), dim3(256), 0, st, coords, N, bits, W,
+                     nrt, nct);
+  return hipGetLastError();
+}
+
+template <int D>
+hipError_t launch_d(int64_t N, const double* coords, uint64_t* bits, int64_t W, hipStream_t st) {
+  // the tallest tile that still leaves enough tiles to fill the chip
+  constexpr int64_t kEnough = 2048;
+  if (tile_count<8>(N, W) >= kEnough) return launch_r<D, 8>(N, coords, bits, W, st);
+  if (tile_count<4>(N, W) >= kEnough) return launch_r<D, 4>(N, coords, bits, W, st);
+  if (tile_count<2>(N, W) >= kEnough) return launch_r<D, 2>(N, coords, bits, W, st);
+  return launch_r<D, 1>(N, coords, bits, W, st);
+}
+}  // namespace
+
+int64_t batch_link_tiles(int64_t N, int64_t W, int64_t* nrt, int64_t* nct) {
+  const int64_t nb = (N + 63) / 64;
+  *nrt = (nb + kBatchR - 1) / kBatchR;
+  *nct = (W + kLT - 1) / kLT;
+  return tiles_before<kBatchR>(*nrt, *nct);
+}
+
+int64_t batch_link_first_col(int64_t ti) { return first_col_tile<kBatchR>(ti); }
+
 hipError_t launch_link(int d, int64_t N, const double* coords, uint64_t* bits,
                        int64_t W, hipStream_t st) {
   if (N <= 0) return hipSuccess;
-  dim3 grid((unsigned)((W + 63) / 64), (unsigned)((N + 63) / 64));
-  // Column words per pass over the 64 rows: 4 by default (2D N=2^17: 1 word
-  // 3.7 ms, 2 words 2.3 ms); CS_LINK_VARIANT = 1 or 2 selects 1 or 2 for timing.
-  const char* ev = getenv("CS_LINK_VARIANT");
-  const int nw = ev && ev[0] == '1' ? 1 : (ev && ev[0] == '2' ? 2 : 4);
-  if (nw == 4) {
-    if (d == 2)
-      hipLaunchKernelGGL((k_link<2, 4>), grid, dim3(256), 0, st, coords, N, bits, W);
-    else if (d == kLinkDeSitter)
-      hipLaunchKernelGGL((k_link<3, 4>), grid, dim3(256), 0, st, coords, N, bits, W);
-    else
-      hipLaunchKernelGGL((k_link<4, 4>), grid, dim3(256), 0, st, coords, N, bits, W);
-  } else if (nw == 2) {
-    if (d == 2)
-      hipLaunchKernelGGL((k_link<2, 2>), grid, dim3(256), 0, st, coords, N, bits, W);
-    else if (d == kLinkDeSitter)
-      hipLaunchKernelGGL((k_link<3, 2>), grid, dim3(256), 0, st, coords, N, bits, W);
-    else
-      hipLaunchKernelGGL((k_link<4, 2>), grid, dim3(256), 0, st, coords, N, bits, W);
-  } else {
-    if (d == 2)
-      hipLaunchKernelGGL((k_link<2, 1>), grid, dim3(256), 0, st, coords, N, bits, W);
-    else if (d == kLinkDeSitter)
-      hipLaunchKernelGGL((k_link<3, 1>), grid, dim3(256), 0, st, coords, N, bits, W);
-    else
-      hipLaunchKernelGGL((k_link<4, 1>), grid, dim3(256), 0, st, coords, N, bits, W);
-  }
-  return hipGetLastError();
+  if (d == 2) return launch_d<2>(N, coords, bits, W, st);
+  if (d == kLinkDeSitter) return launch_d<3>(N, coords, bits, W, st);
+  return launch_d<4>(N, coords, bits, W, st);
 }
 
 hipError_t launch_batch_link(const BatchDev& b, hipStream_t st) {

@@ -6,6 +6,8 @@ the oracle's arithmetic and justify the change in the commit message.
 
     python tests/golden/make_golden.py            # small and medium workloads
     python tests/golden/make_golden.py --large    # also the 2D N=131072 workload
+    python tests/golden/make_golden.py --plans    # the 512-set ensemble and a
+                                                  # sample of the served stream
 """
 from __future__ import annotations
 
@@ -22,6 +24,7 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
+import causet_inputs as ci  # noqa: E402
 import oracle  # noqa: E402
 
 OUT = os.path.join(HERE, "oracle_reference.json")
@@ -58,15 +61,54 @@ def run_case(d, N, seed, full):
     return rec
 
 
+# The served stream's stored sample: every SERVED_STEP-th request of the
+# 10,000-request plan.
+SERVED_REQUESTS = 10000
+SERVED_STEP = 50
+
+
+def plan_record(d, N, seed):
+    """Abundances, R, sum of interior counts and the action of one sprinkled
+    set, as the plan tests compare them."""
+    coords, _, _ = oracle.sprinkle(d, N, seed)
+    bits = oracle.link(d, coords)
+    hist, R, summ = oracle.count_bits(bits, N, nbins=4)
+    S = oracle.bd_action(d, N, hist[:4])
+    return {"d": d, "N": N, "seed": seed, "n": [int(x) for x in hist[:4]], "R": R,
+            "summ": summ, "S": S.hex()}
+
+
+def run_plans(data):
+    t0 = time.time()
+    data["ensemble_512"] = [plan_record(d, N, seed) for d, N, seed in ci.ensemble_plan(512)]
+    print("ensemble_512: %.1f s" % (time.time() - t0), flush=True)
+    plan = ci.request_plan(SERVED_REQUESTS)
+    sample = []
+    t0 = time.time()
+    for q in range(0, SERVED_REQUESTS, SERVED_STEP):
+        _, d, N, seed = plan[q]
+        rec = plan_record(d, N, seed)
+        rec["q"] = q
+        sample.append(rec)
+        print("served q=%d d=%d N=%d: %.1f s" % (q, d, N, time.time() - t0), flush=True)
+    data["served_sample"] = {"requests": SERVED_REQUESTS, "step": SERVED_STEP, "results": sample}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--large", action="store_true")
     ap.add_argument("--only", default=None)
+    ap.add_argument("--plans", action="store_true")
     a = ap.parse_args()
     data = {}
     if os.path.exists(OUT):
         with open(OUT) as f:
             data = json.load(f)
+    if a.plans:
+        run_plans(data)
+        with open(OUT, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        return
     for name, (d, N, seed, full) in CASES.items():
         if a.only and name != a.only:
             continue

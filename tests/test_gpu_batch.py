@@ -59,23 +59,32 @@ def test_batch_mixed_sizes_match_per_set_and_oracle(cs, ctx):
             assert r["S"] == oracle.bd_action(d, N, h)
 
 
-@pytest.mark.parametrize("mode", ["1", "3"])
-def test_batch_count_path_settings_agree(cs, ctx, monkeypatch, mode):
-    """CS_BATCH_PATH=1 (every set on the popcount kernel) and 3 (the tuner's
-    choice per set) give the default batch's results, which equal the
-    per-set path.  A fresh context per setting: plans are cached per
-    context and batch shape."""
-    say("case batch path mode %s" % mode)
+def test_batch_tuner_keeps_results_and_reports_its_choices(cs):
+    """A fresh context tunes the batch on its first call: every (d, N-bucket)
+    group is counted by the popcount kernel and by both matrix-core tile
+    shapes (the tuner itself fails the batch if any candidate's counts
+    differ), and the chosen kinds cover every set.  A second context that
+    already knows the groups reuses the choices.  Results equal the per-set
+    path both times."""
+    say("case batch tuner")
     plan = MIXED[:12]
-    refs = [per_set(cs, ctx, *p) for p in plan]
-    monkeypatch.setenv("CS_BATCH_PATH", mode)
-    c2 = cs.cs_create(0, 0, None)
+    c1 = cs.cs_create(0, 0, None)
     try:
-        res = cs.cs_batch_run(c2, plan)
+        refs = [per_set(cs, c1, *p) for p in plan]
+        res = cs.cs_batch_run(c1, plan)
+        assert res == refs
+        info = cs.cs_batch_last_info(c1)
+        counted = sum(1 for d, N, _ in plan if N >= 2)
+        assert info["sets_pop"] + info["sets_mfma256"] + info["sets_mfma128"] == counted, info
+        assert info["count_ms_untuned"] > 0 and info["count_ms_tuned"] > 0, info
+        for k in ("pop", "mfma256", "mfma128"):
+            assert (info["grid_" + k] > 0) == (info["sets_" + k] > 0), info
+        # same context, new shape containing the same groups: no new tuning of
+        # those groups, same results as alone
+        plan2 = plan[::-1]
+        assert cs.cs_batch_run(c1, plan2) == refs[::-1]
     finally:
-        cs.cs_destroy(c2)
-    for p, r, ref in zip(plan, res, refs):
-        assert r == ref, (mode, p, r, ref)
+        cs.cs_destroy(c1)
 
 
 def test_ensemble_means_match_2d_expectations(cs, ctx):
@@ -122,16 +131,29 @@ def test_invalid_requests_get_their_own_status(cs, ctx):
     assert res[4] == per_set(cs, ctx, 4, 100, 5)
 
 
+def stored(name):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "oracle_reference.json")) as f:
+        return json.load(f)[name]
+
+
 def test_ensemble_workload_512_sets(cs, ctx):
     """The 512-set ensemble (N uniform in [256, 4096], d in {2, 4}): every set
-    equals its own per-set run."""
+    equals the oracle (stored by tests/golden/make_golden.py from oracle/
+    only) and its own per-set run."""
     say("case ensemble 512")
     plan = ci.ensemble_plan(512)
+    ref = stored("ensemble_512")
     res = cs.cs_batch_run(ctx, plan)
+    for k, ((d, N, seed), r, o) in enumerate(zip(plan, res, ref)):
+        assert (o["d"], o["N"], o["seed"]) == (d, N, seed), k
+        assert r["n"] == o["n"] and r["R"] == o["R"] and r["summ"] == o["summ"], (k, r, o)
+        assert r["S"] == float.fromhex(o["S"]) and r["status"] == 0, (k, r, o)
     for k in range(0, 512, 1):
         d, N, seed = plan[k]
         assert res[k] == per_set(cs, ctx, d, N, seed), k
-    # and a sample against the oracle
+    # and a few computed by the oracle here, not read back
     for k in (0, 1, 2, 3, 100, 511):
         d, N, seed = plan[k]
         oc, _, _ = oracle.sprinkle(d, N, seed)

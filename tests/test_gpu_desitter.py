@@ -96,11 +96,9 @@ def test_full_size_sampled_row_blocks(cs, ctx):
         cs.cs_set_free(s)
 
 
-@pytest.mark.parametrize("variant", ["1", "2", "4"])
-def test_link_variants_match_oracle(cs, ctx, monkeypatch, variant):
-    monkeypatch.setenv("CS_LINK_VARIANT", variant)
-    N, seed = 3000, 41
-    say("case desitter link variant %s" % variant)
+@pytest.mark.parametrize("N,seed", [(3000, 41), (513, 42), (1024, 43)])
+def test_link_ragged_sizes_match_oracle(cs, ctx, N, seed):
+    say("case desitter link N=%d" % N)
     s = cs.cs_sprinkle_desitter(ctx, N, seed, ETA0)
     try:
         cs.cs_link(ctx, s)

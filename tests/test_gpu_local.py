@@ -132,21 +132,6 @@ def test_local_blocks_match_oracle(cs, ctx, d, N, seed):
         cs.cs_set_free(s)
 
 
-@pytest.mark.parametrize("chunk,extra", [(1, 0), (1, 7), (2, 7), (4, 0), (4, 6), (8, 4),
-                                         (14, 1), (14, 0), (3, 5)])
-def test_local_chunk_and_margin_settings(cs, ctx, monkeypatch, chunk, extra):
-    say("case local C=%d E=%d" % (chunk, extra))
-    monkeypatch.setenv("CS_SAT_CHUNK", str(chunk))
-    monkeypatch.setenv("CS_SAT_EXTRA", str(extra))
-    for d, N, seed in ((2, 6000, 31), (4, 4000, 32)):
-        s = cs.cs_sprinkle(ctx, d, N, seed)
-        try:
-            cs.cs_link(ctx, s)
-            check_set(cs, ctx, s, oracle_bits(d, N, seed), N, d)
-        finally:
-            cs.cs_set_free(s)
-
-
 def test_local_device_tier(cs):
     """cs_count_local_dev on torch tensors, row stride wider than W, two
     workspace sizes, two calls in a row on one workspace (the counters are

@@ -92,41 +92,37 @@ def test_counts_match_oracle(cs, ctx, d, N, seed, path):
         cs.cs_set_free(s)
 
 
-@pytest.mark.parametrize("variant", ["1", "2", "4"])
-def test_every_link_variant_matches_oracle(cs, ctx, monkeypatch, variant):
-    """The link kernel's one-, two- and four-words-per-pass forms
-    (CS_LINK_VARIANT; four is the default) write the oracle's matrix, 2D and
-    4D, ragged sizes."""
-    monkeypatch.setenv("CS_LINK_VARIANT", variant)
-    for d, N, seed in ((2, 2049, 8), (2, 4100, 9), (4, 3001, 11), (4, 300, 12)):
-        say("case link variant %s d=%d N=%d" % (variant, d, N))
-        s = gpu_set(cs, ctx, d, N, seed)
-        try:
-            oc, _, _ = oracle.sprinkle(d, N, seed)
-            assert np.array_equal(cs.cs_get_bitset(ctx, s), oracle.link(d, oc))
-        finally:
-            cs.cs_set_free(s)
+@pytest.mark.parametrize("d,N,seed", [(2, 2049, 8), (2, 4100, 9), (4, 3001, 11), (4, 300, 12),
+                                      (2, 511, 13), (2, 512, 14), (2, 513, 15), (4, 1025, 16),
+                                      (2, 1537, 17), (4, 64, 18), (2, 65, 19), (2, 3, 20)])
+def test_link_ragged_sizes_match_oracle(cs, ctx, d, N, seed):
+    """The link writes the oracle's matrix byte for byte at sizes on and
+    around the 64-label blocks and the 512-label tiles, 2D and 4D."""
+    say("case link d=%d N=%d" % (d, N))
+    s = gpu_set(cs, ctx, d, N, seed)
+    try:
+        oc, _, _ = oracle.sprinkle(d, N, seed)
+        assert np.array_equal(cs.cs_get_bitset(ctx, s), oracle.link(d, oc))
+    finally:
+        cs.cs_set_free(s)
 
 
-@pytest.mark.parametrize("d,N,seed", [(2, 700, 7), (4, 1500, 8)])
-def test_every_mfma_variant_matches_oracle(cs, ctx, monkeypatch, d, N, seed):
-    """Every matrix-core kernel form selectable with CS_MFMA_VARIANT (the
-    default and the measured alternatives), int8 and fp4, N_0..N_3 and the
-    full histogram: bins, R and the sum of interior counts equal the
-    oracle's.  (The full-histogram builds of the 2x2-wave and prefetching
-    forms once returned a wrong sum of interior counts with correct bins.)"""
-    say("case every variant d=%d N=%d" % (d, N))
+@pytest.mark.parametrize("d,N,seed", [(2, 700, 7), (4, 1500, 8), (2, 3000, 2)])
+def test_mfma_paths_every_histogram_length_match_oracle(cs, ctx, d, N, seed):
+    """Both matrix-core operand types, N_0..N_3, 41 bins and the full
+    histogram: bins, R and the sum of interior counts equal the oracle's.
+    (2D N=3000 with 41 bins is where a removed 2x2-wave int8 form once
+    returned a wrong sum of interior counts with correct bins.)"""
+    say("case mfma histograms d=%d N=%d" % (d, N))
     s = gpu_set(cs, ctx, d, N, seed)
     try:
         oc, _, _ = oracle.sprinkle(d, N, seed)
         ob = oracle.link(d, oc)
-        want = {k: oracle.count_bits(ob, N, nbins=k + 1) for k in (3, 40, N - 2)}
-        for v in range(14):
-            monkeypatch.setenv("CS_MFMA_VARIANT", str(v))
+        for k in (3, 40, N - 2):
+            h, oR, osm = oracle.count_bits(ob, N, nbins=k + 1)
             for path in (2, 3):
-                for k, (h, oR, osm) in want.items():
-                    n, R, sm = cs.cs_interval_abundances(ctx, s, k, path)
-                    assert np.array_equal(n, h) and R == oR and sm == osm, (v, path, k)
+                n, R, sm = cs.cs_interval_abundances(ctx, s, k, path)
+                assert np.array_equal(n, h) and R == oR and sm == osm, (path, k)
     finally:
         cs.cs_set_free(s)
 

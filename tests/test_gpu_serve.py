@@ -7,6 +7,7 @@ import time
 import pytest
 
 import causet_inputs as ci
+import oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -20,6 +21,20 @@ def say(*a):
 def cs():
     import paper_1709_03013_amd as p
     return p
+
+
+def oracle_result(d, N, seed):
+    oc, _, _ = oracle.sprinkle(d, N, seed)
+    h, R, sm = oracle.count_bits(oracle.link(d, oc), N, nbins=4) if N > 0 else ([0] * 4, 0, 0)
+    return {"n": [int(x) for x in h[:4]], "R": R, "summ": sm,
+            "S": oracle.bd_action(d, N, h[:4]) if N > 0 else oracle.bd_action(d, 0, [0] * 4), "status": 0}
+
+
+def stored(name):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "oracle_reference.json")) as f:
+        return json.load(f)[name]
 
 
 def alone(cs, ctx, d, N, seed):
@@ -58,6 +73,8 @@ def test_results_in_the_mix_equal_alone(cs):
     ctx = cs.cs_create(0, 0, None)
     try:
         refs = [alone(cs, ctx, *r) for r in MIX]
+        for req, ref in zip(MIX, refs):
+            assert ref == oracle_result(*req), req
         cs.cs_queue_start(ctx, 4, 0)
         res = run_all(cs, ctx, MIX)
         for req, (r, tm), ref in zip(MIX, res, refs):
@@ -91,6 +108,37 @@ def test_binding_budget_admits_as_memory_frees(cs):
         cs.cs_destroy(big)
 
 
+def test_completion_order_interface(cs):
+    """cs_queue_next hands out every finished request exactly once, in
+    completion order, with the same results as polling by ticket; it times
+    out with nothing pending."""
+    say("case serve next")
+    reqs = [(2, 3000 + 100 * k, 300 + k) for k in range(6)] + [(4, 2000, 400), (2, 512, 401)]
+    ctx = cs.cs_create(0, 0, None)
+    try:
+        refs = {r: alone(cs, ctx, *r) for r in reqs}
+        cs.cs_queue_start(ctx, 3, 0)
+        assert cs.cs_queue_next(ctx, 0.0) is None
+        tickets = {cs.cs_queue_submit(ctx, *r): r for r in reqs}
+        got = {}
+        t0 = time.time()
+        while len(got) < len(reqs):
+            r = cs.cs_queue_next(ctx, 1.0)
+            assert time.time() - t0 < 120
+            if r is None:
+                continue
+            t, res, tm = r
+            assert t in tickets and t not in got
+            assert res == refs[tickets[t]] and 0 <= tm[0] <= tm[2]
+            got[t] = res
+        assert cs.cs_queue_next(ctx, 0.05) is None
+        # a ticket returned by cs_queue_next cannot be polled again
+        with pytest.raises(cs.CsError):
+            cs.cs_queue_poll(ctx, next(iter(tickets)))
+    finally:
+        cs.cs_destroy(ctx)
+
+
 def test_queue_errors(cs):
     ctx = cs.cs_create(0, 0, None)
     try:
@@ -112,7 +160,8 @@ def test_queue_errors(cs):
 
 
 def test_request_plan_sample(cs):
-    """A sample of the served workload (N log-uniform in [512, 32768])."""
+    """A sample of the served workload (N log-uniform in [512, 32768]): every
+    queued result equals the same request alone."""
     say("case serve plan sample")
     plan = ci.request_plan(60)
     reqs = [(d, N, seed) for _, d, N, seed in plan]
@@ -122,5 +171,48 @@ def test_request_plan_sample(cs):
         cs.cs_queue_start(ctx, 4, 0)
         res = run_all(cs, ctx, reqs)
         assert [r for r, _ in res] == refs
+    finally:
+        cs.cs_destroy(ctx)
+
+
+def test_served_stream_sample_equals_oracle(cs):
+    """Every 50th request of the 10,000-request served stream (200 requests,
+    N up to 32768, both dimensions), queued together on 4 slots: each result
+    equals the oracle's (stored by tests/golden/make_golden.py from oracle/
+    only), bit for bit."""
+    say("case serve vs oracle")
+    sample = stored("served_sample")
+    plan = ci.request_plan(sample["requests"])
+    reqs = []
+    for o in sample["results"]:
+        _, d, N, seed = plan[o["q"]]
+        assert (o["d"], o["N"], o["seed"]) == (d, N, seed), o["q"]
+        reqs.append((d, N, seed))
+    ctx = cs.cs_create(0, 0, None)
+    try:
+        cs.cs_queue_start(ctx, 4, 0)
+        res = run_all(cs, ctx, reqs, timeout_s=300)
+        for o, (r, _) in zip(sample["results"], res):
+            assert r["status"] == 0, o["q"]
+            assert r["n"] == o["n"] and r["R"] == o["R"] and r["summ"] == o["summ"], (o["q"], r, o)
+            assert r["S"] == float.fromhex(o["S"]), (o["q"], r, o)
+    finally:
+        cs.cs_destroy(ctx)
+
+
+def test_repeated_request_in_flight_waits_for_its_matrix(cs):
+    """The same large request submitted several times back to back on four
+    slots, twice over: a repeat must not read the resident matrix while the
+    first copy is still building it.  Every result equals the oracle's."""
+    say("case serve repeats in flight")
+    reqs = [(2, 24000, 77)] * 4 + [(4, 16000, 78)] * 4 + [(2, 24000, 77), (4, 16000, 78)] * 2
+    want = {r: oracle_result(*r) for r in set(reqs)}
+    ctx = cs.cs_create(0, 0, None)
+    try:
+        cs.cs_queue_start(ctx, 4, 0)
+        for rnd in range(2):
+            res = run_all(cs, ctx, reqs)
+            for req, (r, _) in zip(reqs, res):
+                assert r == want[req], (rnd, req, r, want[req])
     finally:
         cs.cs_destroy(ctx)
