@@ -231,6 +231,23 @@ cs_status cs_count_dev(const uint64_t* bits_dev, int64_t N,
                        int64_t stride_words, int kmax, uint64_t* stats_dev,
                        void* work_dev, int path, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the count
+ * of cs_count_dev with its workspace in a fixed device array of the library
+ * (CS_COUNT_STATIC_WORDS uint64 words, 1 MiB, held on every device the
+ * library runs on until the process ends) instead of a caller's buffer.
+ * Allocates nothing; the caller still owns bits_dev and stats_dev (kmax+3
+ * words, overwritten).  CS_EINVAL if cs_count_workspace_bytes(N, kmax)
+ * exceeds the array (e.g. N = 2^17 allows kmax <= 253), or for the
+ * arguments cs_count_dev rejects.  path CS_PATH_AUTO uses the fixed size
+ * threshold (no timing runs).  The array is cleared by a kernel at the start
+ * of every call; calls that overlap on one device (other streams, other
+ * threads) share it and race. */
+#define CS_COUNT_STATIC_WORDS 131072
+cs_status cs_count_dev_static(const uint64_t* bits_dev, int64_t N,
+                              int64_t stride_words, int kmax, uint64_t* stats_dev,
+                              int path, void* hip_stream);
+
 /* Local abundances from a device matrix (the saturating count above).
  * stats_dev receives 6 uint64 words: N_0..N_3, R, pairs continued from HBM.
  * work_dev: device scratch of work_bytes >= cs_count_local_workspace_bytes(N)

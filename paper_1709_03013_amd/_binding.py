@@ -87,6 +87,8 @@ _SIGS = {
     "cs_count_workspace_bytes": (ctypes.c_uint64, [ctypes.c_int64, ctypes.c_int]),
     "cs_count_dev": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, _vp, _vp,
                                     ctypes.c_int, _vp]),
+    "cs_count_dev_static": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, _vp,
+                                           ctypes.c_int, _vp]),
     "cs_local_abundances": (ctypes.c_int, [_vp, _vp, _u64p, _u64p]),
     "cs_count_local_workspace_bytes": (ctypes.c_uint64, [ctypes.c_int64]),
     "cs_count_local_dev": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int64, _vp, _vp,
@@ -313,6 +315,14 @@ def cs_count_workspace_bytes(N: int, kmax: int) -> int:
 def cs_count_dev(bits_dev: int, N: int, stride_words: int, kmax: int, stats_dev: int, work_dev: int,
                  path: int, hip_stream: int | None):
     _check(lib().cs_count_dev(bits_dev, N, stride_words, kmax, stats_dev, work_dev, path, hip_stream))
+
+
+COUNT_STATIC_WORDS = 131072
+
+
+def cs_count_dev_static(bits_dev: int, N: int, stride_words: int, kmax: int, stats_dev: int,
+                        path: int, hip_stream: int | None):
+    _check(lib().cs_count_dev_static(bits_dev, N, stride_words, kmax, stats_dev, path, hip_stream))
 
 
 def make_reqs(plan):

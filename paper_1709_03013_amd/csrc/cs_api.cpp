@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -603,6 +604,61 @@ cs_status cs_count_dev(const uint64_t* bits_dev, int64_t N, int64_t stride_words
   return e == hipSuccess ? CS_OK : hip_fail(e, "cs_count_dev");
 }
 
+
+// ---- the count with a library-held workspace ----------------------------------
+// A fixed device array stands in for the caller's workspace.  Its name in
+// host code is not a device address: each device's copy is looked up once
+// with hipGetSymbolAddress (with that device current) and only that pointer
+// is handed to kernels.
+namespace {
+static __device__ __align__(256) uint64_t scratch[CS_COUNT_STATIC_WORDS];
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_dev;  // per device id
+}  // namespace
+
+static cs_status scratch_for_current_device(uint64_t** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "cs_count_dev_static: hipGetDevice");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if ((size_t)dev >= g_scratch_dev.size()) g_scratch_dev.resize((size_t)dev + 1, nullptr);
+  if (!g_scratch_dev[(size_t)dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e, "cs_count_dev_static: hipGetSymbolAddress");
+    g_scratch_dev[(size_t)dev] = p;
+  }
+  *out = (uint64_t*)g_scratch_dev[(size_t)dev];
+  return CS_OK;
+}
+
+cs_status cs_count_dev_static(const uint64_t* bits_dev, int64_t N, int64_t stride_words, int kmax,
+                              uint64_t* stats_dev, int path, void* hip_stream) {
+  if (N < 0) return fail(CS_EINVAL, "cs_count_dev_static: N < 0");
+  if (kmax < 3 || kmax > CS_KMAX_MAX) return fail(CS_EINVAL, "cs_count_dev_static: bad kmax %d", kmax);
+  if (path < CS_PATH_AUTO || path > CS_PATH_MFMA_FP4) return fail(CS_EINVAL, "cs_count_dev_static: bad path");
+  if (path == CS_PATH_MFMA_FP4 && N >= (1 << 24))
+    return fail(CS_EINVAL, "cs_count_dev_static: the FP4 path needs N < 2^24");
+  if (!stats_dev || (N > 0 && !bits_dev)) return fail(CS_EINVAL, "cs_count_dev_static: NULL pointer");
+  if (N > 0 && (stride_words < row_words(N) || stride_words % 4))
+    return fail(CS_EINVAL, "cs_count_dev_static: stride must be >= %lld and a multiple of 4",
+                (long long)row_words(N));
+  const int64_t nrb = num_row_blocks(N);
+  const uint64_t nws = (uint64_t)(nrb > 0 ? nrb : 1) * (uint64_t)(kmax + 3);
+  if (nws > CS_COUNT_STATIC_WORDS)
+    return fail(CS_EINVAL, "cs_count_dev_static: N=%lld with kmax=%d needs %llu workspace words, "
+                "more than the library's %d", (long long)N, kmax, (unsigned long long)nws,
+                CS_COUNT_STATIC_WORDS);
+  uint64_t* ws = nullptr;
+  cs_status rc = scratch_for_current_device(&ws);
+  if (rc != CS_OK) return rc;
+  hipStream_t st = (hipStream_t)hip_stream;
+  hipError_t e = init_count_mfma();
+  if (e == hipSuccess) e = launch_fill_u64(ws, 0, (size_t)nws, st);
+  if (e == hipSuccess && N > 1) e = run_count(bits_dev, N, stride_words, kmax, path, ws, st);
+  if (e == hipSuccess) e = launch_reduce_rows(ws, nrb > 0 ? nrb : 1, kmax, stats_dev, st);
+  return e == hipSuccess ? CS_OK : hip_fail(e, "cs_count_dev_static");
+}
 
 // ---- local abundances by the saturating count -------------------------------
 

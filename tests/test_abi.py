@@ -73,6 +73,27 @@ def test_argument_errors_need_no_device(lib):
     assert lib.cs_count_workspace_bytes(1000, 3) == 4 * 6 * 8
 
 
+def test_static_workspace_count_refuses_before_any_device_work(lib):
+    """cs_count_dev_static checks its arguments and the size of the library's
+    array (CS_COUNT_STATIC_WORDS words) before touching a device."""
+    EINVAL = lib._binding.CS_EINVAL
+    W = lib.cs_row_words(131072)
+    cases = [(131072, W, 300, 3),      # 512 row blocks x 303 words > 131072
+             (2 ** 20, lib.cs_row_words(2 ** 20), 30, 2),
+             (100, 4, 2, 1),           # kmax < 3
+             (100, 4, 3, 9),           # bad path
+             (100, 2, 3, 1),           # stride below W
+             (-1, 4, 3, 1)]
+    for N, stride, kmax, path in cases:
+        with pytest.raises(lib.CsError) as e:
+            lib.cs_count_dev_static(1, N, stride, kmax, 1, path, None)
+        assert e.value.status == EINVAL, (N, stride, kmax, path)
+    assert lib._binding.COUNT_STATIC_WORDS == 131072
+    # the largest full histogram that fits at N = 2^17: 512 * (253 + 3) words
+    assert lib.cs_count_workspace_bytes(131072, 253) // 8 <= lib._binding.COUNT_STATIC_WORDS
+    assert lib.cs_count_workspace_bytes(131072, 254) // 8 > lib._binding.COUNT_STATIC_WORDS
+
+
 def test_local_count_argument_errors_need_no_device(lib):
     EINVAL = lib._binding.CS_EINVAL
     ws = lambda N: 64 * max((N + 63) // 64, 1)
