@@ -219,10 +219,17 @@ cs_status cs_smeared_action(cs_ctx* ctx, cs_set* set, double eps, double* S_out)
 /* The caller owns all memory and the stream; calls are asynchronous on
  * `hip_stream` (a hipStream_t; NULL = the legacy default stream).
  * coords_dev: d*N doubles (SoA, topologically sorted).  bits_dev: N rows of
- * stride_words (>= cs_row_words(N), multiple of 4) words. */
+ * stride_words (>= cs_row_words(N), multiple of 4) words.
+ * The link (Sec. 2.2) of a flat diamond.  In 2D it needs device scratch of
+ * cs_link_workspace_bytes(2, N) bytes (per block of 64 labels: its sorted
+ * u and v values and prefix masks, 2112 bytes), in use until the link has
+ * finished on hip_stream; in 4D the size is 0 and work_dev may be NULL.
+ * CS_EINVAL for d not 2 or 4, N < 0, a bad stride, NULL pointers or a
+ * workspace below the size; nothing is launched then. */
+uint64_t cs_link_workspace_bytes(int d, int64_t N);
 cs_status cs_link_dev(int d, int64_t N, const double* coords_dev,
                       uint64_t* bits_dev, int64_t stride_words,
-                      void* hip_stream);
+                      void* work_dev, uint64_t work_bytes, void* hip_stream);
 /* Count from a device matrix.  stats_dev receives kmax+3 uint64 words:
  * N_0..N_kmax, R, sum of interior counts (device memory, overwritten).
  * work_dev: device scratch of cs_count_workspace_bytes(N, kmax) bytes. */

@@ -83,7 +83,9 @@ _SIGS = {
     "cs_interval_abundances_rows": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _u64p, ctypes.c_int]),
     "cs_bd_action": (ctypes.c_int, [_vp, _vp, _dp]),
     "cs_smeared_action": (ctypes.c_int, [_vp, _vp, ctypes.c_double, _dp]),
-    "cs_link_dev": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp]),
+    "cs_link_workspace_bytes": (ctypes.c_uint64, [ctypes.c_int, ctypes.c_int64]),
+    "cs_link_dev": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp,
+                                   ctypes.c_uint64, _vp]),
     "cs_count_workspace_bytes": (ctypes.c_uint64, [ctypes.c_int64, ctypes.c_int]),
     "cs_count_dev": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, _vp, _vp,
                                     ctypes.c_int, _vp]),
@@ -304,8 +306,13 @@ def cs_smeared_action(ctx: int, s: int, eps: float) -> float:
     return S.value
 
 
-def cs_link_dev(d: int, N: int, coords_dev: int, bits_dev: int, stride_words: int, hip_stream: int | None):
-    _check(lib().cs_link_dev(d, N, coords_dev, bits_dev, stride_words, hip_stream))
+def cs_link_workspace_bytes(d: int, N: int) -> int:
+    return int(lib().cs_link_workspace_bytes(d, N))
+
+
+def cs_link_dev(d: int, N: int, coords_dev: int, bits_dev: int, stride_words: int, work_dev: int | None,
+                work_bytes: int, hip_stream: int | None):
+    _check(lib().cs_link_dev(d, N, coords_dev, bits_dev, stride_words, work_dev, work_bytes, hip_stream))
 
 
 def cs_count_workspace_bytes(N: int, kmax: int) -> int:

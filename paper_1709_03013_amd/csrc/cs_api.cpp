@@ -429,6 +429,7 @@ void cs_set_free(cs_set* s) {
     s->ctx->pool.release(s->coords);
     s->ctx->pool.release(s->orig);
     s->ctx->pool.release(s->bits);
+    s->ctx->pool.release(s->link_work);
   }
   delete s;
 }
@@ -480,7 +481,17 @@ cs_status cs_link(cs_ctx* ctx, cs_set* s) {
       return fail(CS_ENOMEM, "cs_link: matrix of %llu bytes exceeds the HBM budget",
                   (unsigned long long)((size_t)s->N * s->W * 8));
     const int kind = s->manifold == CS_MANIFOLD_DESITTER ? kLinkDeSitter : s->d;
-    hipError_t e = launch_link(kind, s->N, s->coords, s->bits, s->W, ctx->stream);
+    const size_t wb = link_workspace_bytes(kind, s->N);
+    if (wb) {
+      s->link_work = ctx->pool.alloc(wb);
+      if (!s->link_work) {
+        ctx->pool.release(s->bits);
+        s->bits = nullptr;
+        return fail(CS_ENOMEM, "cs_link: link tables of %llu bytes exceed the HBM budget",
+                    (unsigned long long)wb);
+      }
+    }
+    hipError_t e = launch_link(kind, s->N, s->coords, s->bits, s->W, s->link_work, ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "link launch");
   }
   s->linked = true;
@@ -566,15 +577,24 @@ cs_status cs_smeared_action(cs_ctx* ctx, cs_set* s, double eps, double* S_out) {
   return CS_OK;
 }
 
+uint64_t cs_link_workspace_bytes(int d, int64_t N) {
+  if ((d != 2 && d != 4) || N < 0) return 0;
+  return (uint64_t)link_workspace_bytes(d, N);
+}
+
 cs_status cs_link_dev(int d, int64_t N, const double* coords_dev, uint64_t* bits_dev, int64_t stride_words,
-                      void* hip_stream) {
+                      void* work_dev, uint64_t work_bytes, void* hip_stream) {
   if (d != 2 && d != 4) return fail(CS_EINVAL, "cs_link_dev: d must be 2 or 4");
   if (N < 0) return fail(CS_EINVAL, "cs_link_dev: N < 0");
   if (N == 0) return CS_OK;
   if (!coords_dev || !bits_dev) return fail(CS_EINVAL, "cs_link_dev: NULL pointer");
   if (stride_words < row_words(N) || stride_words % 4)
     return fail(CS_EINVAL, "cs_link_dev: stride must be >= %lld and a multiple of 4", (long long)row_words(N));
-  hipError_t e = launch_link(d, N, coords_dev, bits_dev, stride_words, (hipStream_t)hip_stream);
+  const uint64_t need = (uint64_t)link_workspace_bytes(d, N);
+  if (need && (!work_dev || work_bytes < need))
+    return fail(CS_EINVAL, "cs_link_dev: workspace of %llu bytes needed, %llu given", (unsigned long long)need,
+                (unsigned long long)(work_dev ? work_bytes : 0));
+  hipError_t e = launch_link(d, N, coords_dev, bits_dev, stride_words, work_dev, (hipStream_t)hip_stream);
   return e == hipSuccess ? CS_OK : hip_fail(e, "cs_link_dev");
 }
 

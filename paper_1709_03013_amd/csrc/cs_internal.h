@@ -57,8 +57,12 @@ hipError_t launch_sprinkle_desitter(int64_t N, uint64_t seed, double w0, double*
 constexpr int kLinkDeSitter = 3;
 
 // Link: bits must hold N*W words; every word of every row is written.
+// work: link_workspace_bytes(d, N) bytes of device scratch (2D: the sorted
+// block tables; nothing for the other kinds, work may be null), in use until
+// the link has finished on `st`.
+size_t link_workspace_bytes(int d, int64_t N);
 hipError_t launch_link(int d, int64_t N, const double* coords, uint64_t* bits,
-                       int64_t W, hipStream_t st);
+                       int64_t W, void* work, hipStream_t st);
 
 // Link tiles of one set in a batch: *nrt row tiles, *nct column tiles; the
 // set's items are (ti, tk) for every ti < *nrt and batch_link_first_col(ti)

@@ -68,6 +68,7 @@ struct cs_set {
   double* coords = nullptr;  // rows*N SoA, sorted
   int64_t* orig = nullptr;   // generation index of each sorted element
   uint64_t* bits = nullptr;  // N*W words
+  void* link_work = nullptr; // 2D link tables (link_workspace_bytes), kept until the set is freed
   bool linked = false;
   int counted_kmax = -1;
   int last_path = 0;  // count path used by the last cs_interval_abundances

@@ -90,8 +90,8 @@ static size_t footprint(int d, int64_t N, int64_t ncand, bool need_matrix) {
   const size_t W = (size_t)row_words(N);
   size_t b = (size_t)N * d * 8 + (size_t)N * 8 + sprinkle_scratch_bytes(d, N, ncand) +
              (size_t)std::max<int64_t>(num_row_blocks(N), 1) * 6 * 8 + 6 * 8;
-  if (need_matrix) b += (size_t)N * W * 8;
-  return b + 4 * 256;
+  if (need_matrix) b += (size_t)N * W * 8 + link_workspace_bytes(d, N);
+  return b + 5 * 256;
 }
 
 static Resident* find_resident(QueueState* q, const std::tuple<int, int64_t, uint64_t>& key) {
@@ -193,12 +193,15 @@ static bool launch_request(QueueState* q, Slot& s, std::shared_ptr<Request> rq, 
   double* coords = nullptr;
   int64_t* orig = nullptr;
   void* scratch = nullptr;
+  void* ltab = nullptr;
   if (ok && !res) {
     coords = (double*)grab((size_t)N * d * 8);
     orig = (int64_t*)grab((size_t)N * 8);
     scratch = grab(sprinkle_scratch_bytes(d, N, ncand));
+    const size_t lb = link_workspace_bytes(d, N);
+    if (lb) ltab = grab(lb);
     bits = (uint64_t*)ctx->pool.alloc((size_t)N * W * 8);
-    ok = coords && orig && scratch && bits;
+    ok = coords && orig && scratch && bits && (ltab || !lb);
   }
   if (!ok) {
     for (void* p : tr) ctx->pool.release(p);
@@ -227,7 +230,7 @@ static bool launch_request(QueueState* q, Slot& s, std::shared_ptr<Request> rq, 
   s.host[6] = (uint64_t)N;  // accepted count, overwritten for 4D
   if (fresh && N > 0) {
     e = launch_sprinkle(d, N, rq->req.seed, ncand, coords, orig, scratch, tot + 6, st);
-    if (e == hipSuccess) e = launch_link(d, N, coords, bits, W, st);
+    if (e == hipSuccess) e = launch_link(d, N, coords, bits, W, ltab, st);
   }
   if (e == hipSuccess) e = launch_fill_u64(ws, 0, (size_t)std::max<int64_t>(num_row_blocks(N), 1) * 6, st);
   if (e == hipSuccess && N > 1) e = run_count(bits, N, W, 3, path, ws, st);

@@ -1,7 +1,28 @@
 // k_link.hip -- the O(N^2) linking step (Sec. 2.2): the packed, symmetric,
 // zero-diagonal causal matrix from time-sorted coordinates.
 //
-// gfx950 design.  Each pair is tested once.  The matrix is cut into blocks
+// 2D flat diamond: order statistics instead of pair tests.  In light-cone
+// coordinates the relation is a dominance order: k is in the future of i iff
+// u_k > u_i and v_k > v_i, in the past iff u_k < u_i and v_k < v_i.  For a
+// block K of 64 labels, sort its u values (and separately its v values)
+// together with their labels, and keep the prefix masks pu[c] = labels of the
+// c smallest u (pv[c] likewise).  Then word K of row i is
+//   past:   pu[#{u_k < u_i}] & pv[#{v_k < v_i}]
+//   future: ~pu[#{u_k <= u_i}] & ~pv[#{v_k <= v_i}]   (existing labels only)
+// where each count is a binary search of the row's coordinate in the block's
+// sorted values: 2 x 7 compares per 64-bit word instead of 2 x 64.  Labels
+// are time-sorted, so blocks before the row's own hold only its past, blocks
+// after it only its future, and its own block both.  Every compare is the
+// same binary64 compare as the definition (strict order, ties unrelated), so
+// the words are bit-identical to testing every pair.  k_block_tables builds
+// the tables (one wave per block: a bitonic sort across the lanes and a
+// prefix OR); k_link2d stages the tables of 8 column blocks in LDS and gives
+// each lane one row: it writes 8 consecutive words (64 bytes) of its row per
+// row block, looping over 16-row-block tall tiles so the tables are loaded
+// once per 1024..4096 rows.
+//
+// 4D flat diamond and de Sitter slab: pair tests.  Each pair is tested once.
+// The matrix is cut into blocks
 // of 64 x 64 labels; block (I, K) with I < K (rows of block I, columns of
 // block K) is tested as 64 wave-wide compares: the 64 lanes are the columns
 // k, the rows i = 64I + r come one at a time as wave-uniform coordinates
@@ -12,9 +33,10 @@
 // block I: word I of row k, the lower-triangle word.  An in-register 64x64
 // bit transpose (permlane / DPP / swizzle exchanges, one bit-field insert
 // per step) turns it into word K of the rows of block I, the upper-triangle
-// word.  So a block costs 64 compare steps (2 compares in 2D, the 4D and de
-// Sitter tests in binary64) plus 64 carry-in adds and one transpose for
-// 4096 pairs, and writes both of its mirror words.
+// word.  So a block costs 64 compare steps (the 4D and de Sitter tests in
+// binary64) plus 64 carry-in adds and one transpose for 4096 pairs, and
+// writes both of its mirror words.  (The batched link uses these pair tests
+// for its 2D sets too.)
 //
 // A workgroup of 4 waves owns a tile of 8 x 8 blocks (512 x 512 labels) of
 // the upper triangle (row tile <= column tile); wave w takes the column
@@ -436,6 +458,156 @@ __global__ __launch_bounds__(256) void k_batch_link(BatchDev b) {
     link_tile<4, kBatchR>(b.coords + bs.coords_off, bs.N, b.bits + bs.bits_off, bs.W, ti, tk, stage);
 }
 
+// ---- 2D by order statistics ------------------------------------------------
+// Table of one block of 64 labels (kTabWords words): su[64] and sv[64] (the
+// block's u and v values sorted ascending, +inf for labels past N), pu[65]
+// and pv[65] (pu[c]: bits of the labels of the c smallest u), then padding.
+constexpr int kTabWords = 264;
+constexpr int kTabSV = 64, kTabPU = 128, kTabPV = 193;
+constexpr int kLink2dKB = 8;  // column blocks (words) per tile
+
+__device__ __forceinline__ double shfl_xor_d(double x, int m) {
+  return __longlong_as_double(__shfl_xor((long long)__double_as_longlong(x), m, 64));
+}
+
+// One wave per block: each coordinate sorted with its labels across the
+// lanes (bitonic, ties by label, so the order is total), then the prefix OR
+// of the labels' bits.
+__global__ __launch_bounds__(256) void k_block_tables(const double* __restrict__ coords, int64_t N,
+                                                      uint64_t* __restrict__ tabs) {
+  const int lane = threadIdx.x & 63;
+  const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t NB = (N + 63) >> 6;
+  if (b >= NB) return;  // whole wave
+  const int64_t e = b * 64 + lane;
+  uint64_t* t = tabs + b * kTabWords;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    double x = e < N ? coords[(int64_t)q * N + e] : __builtin_inf();
+    int idx = lane;
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1)
+#pragma unroll
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        const double ox = shfl_xor_d(x, j);
+        const int oi = __shfl_xor(idx, j, 64);
+        const bool other_less = ox < x || (ox == x && oi < idx);
+        const bool keep_min = ((lane & k) == 0) == ((lane & j) == 0);
+        if (keep_min == other_less) {
+          x = ox;
+          idx = oi;
+        }
+      }
+    uint64_t incl = 1ull << idx;
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) {
+      const uint64_t o = __shfl_up(incl, s, 64);
+      if (lane >= s) incl |= o;
+    }
+    t[q * kTabSV + lane] = (uint64_t)__double_as_longlong(x);
+    t[(q ? kTabPV : kTabPU) + lane + 1] = incl;
+    if (lane == 0) t[q ? kTabPV : kTabPU] = 0ull;
+  }
+}
+
+// x >= +0: the next double above x, so that p <= x iff p < next_up(x).
+__device__ __forceinline__ double next_up(double x) {
+  return __longlong_as_double(__double_as_longlong(x) + 1);
+}
+
+// Count of the sorted a[0..63] below q: six halvings reach 0..63, one more
+// compare decides 64.
+__device__ __forceinline__ int count_below(const double* a, double q) {
+  int c = 0;
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) c += a[c + s - 1] < q ? s : 0;
+  return c + (a[c] < q ? 1 : 0);
+}
+
+// Tile: column blocks K0 .. K0+KB-1 (their tables in LDS) x row blocks
+// 4*(rt*RB + r) + wave for r < RB; lane = row.  The searches of the KB words
+// run level by level so that 2*KB LDS reads are in flight per step.
+template <int KB>
+__global__ __launch_bounds__(256) void k_link2d(const double* __restrict__ coords, int64_t N,
+                                                uint64_t* __restrict__ bits, int64_t W,
+                                                const uint64_t* __restrict__ tabs, int64_t nrt,
+                                                int RB) {
+  __shared__ uint64_t tl[KB * kTabWords];
+  const int64_t rt = (int64_t)blockIdx.x % nrt, ct = (int64_t)blockIdx.x / nrt;
+  const int64_t K0 = ct * KB;
+  const int64_t NB = (N + 63) >> 6;
+  for (int q = threadIdx.x; q < KB * kTabWords; q += 256) {
+    const int64_t K = K0 + q / kTabWords;
+    tl[q] = K < NB ? tabs[K0 * kTabWords + q] : 0ull;
+  }
+  __syncthreads();
+  const double* tld = (const double*)tl;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int rb = 0; rb < RB; ++rb) {
+    const int64_t I = (rt * RB + rb) * 4 + wave;
+    if (I >= NB) break;  // whole wave; no barrier follows
+    const int64_t i = I * 64 + lane;
+    const bool live = i < N;
+    const double xu = live ? coords[i] : 0.0, xv = live ? coords[N + i] : 0.0;
+    const double nu = next_up(xu), nv = next_up(xv);
+    // earlier blocks and the row's own: entries below the row; later
+    // blocks: entries at or below it
+    double qu[KB], qv[KB];
+    int cu[KB], cv[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const bool later = K0 + k > I;
+      qu[k] = later ? nu : xu;
+      qv[k] = later ? nv : xv;
+      cu[k] = 0;
+      cv[k] = 0;
+    }
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1)
+#pragma unroll
+      for (int k = 0; k < KB; ++k) {
+        cu[k] += tld[k * kTabWords + cu[k] + s - 1] < qu[k] ? s : 0;
+        cv[k] += tld[k * kTabWords + kTabSV + cv[k] + s - 1] < qv[k] ? s : 0;
+      }
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      cu[k] += tld[k * kTabWords + cu[k]] < qu[k] ? 1 : 0;
+      cv[k] += tld[k * kTabWords + kTabSV + cv[k]] < qv[k] ? 1 : 0;
+    }
+    uint64_t w[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const int64_t K = K0 + k;
+      const uint64_t a = tl[k * kTabWords + kTabPU + cu[k]], b = tl[k * kTabWords + kTabPV + cv[k]];
+      const uint64_t valid =
+          K * 64 + 64 <= N ? ~0ull : (K * 64 < N ? ((1ull << (N - K * 64)) - 1ull) : 0ull);
+      w[k] = K > I ? (~a & ~b & valid) : (a & b);
+    }
+    // the row's own block also holds the later elements of that block
+    const int64_t kd = I - K0;
+    if (kd >= 0 && kd < KB) {
+#pragma unroll
+      for (int k = 0; k < KB; ++k) {
+        if (k != kd) continue;
+        const int du = count_below(tld + k * kTabWords, nu);
+        const int dv = count_below(tld + k * kTabWords + kTabSV, nv);
+        const int64_t K = K0 + k;
+        const uint64_t valid = K * 64 + 64 <= N ? ~0ull : ((1ull << (N - K * 64)) - 1ull);
+        w[k] |= ~tl[k * kTabWords + kTabPU + du] & ~tl[k * kTabWords + kTabPV + dv] & valid;
+      }
+    }
+    if (live) {
+      uint64_t* row = bits + i * W + K0;
+#pragma unroll
+      for (int k = 0; k < KB; k += 2)
+        if (K0 + k < W)
+          *(uint4*)(row + k) = make_uint4((uint32_t)w[k], (uint32_t)(w[k] >> 32), (uint32_t)w[k + 1],
+                                          (uint32_t)(w[k + 1] >> 32));
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_fill_u64(uint64_t* __restrict__ p,
                                                   uint64_t v, size_t n) {
   size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
@@ -509,10 +681,30 @@ int64_t batch_link_tiles(int64_t N, int64_t W, int64_t* nrt, int64_t* nct) {
 
 int64_t batch_link_first_col(int64_t ti) { return first_col_tile<kBatchR>(ti); }
 
+size_t link_workspace_bytes(int d, int64_t N) {
+  return d == 2 && N > 0 ? (size_t)((N + 63) / 64) * kTabWords * 8 : 0;
+}
+
 hipError_t launch_link(int d, int64_t N, const double* coords, uint64_t* bits,
-                       int64_t W, hipStream_t st) {
+                       int64_t W, void* work, hipStream_t st) {
   if (N <= 0) return hipSuccess;
-  if (d == 2) return launch_d<2>(N, coords, bits, W, st);
+  if (d == 2) {
+    if (!work) return hipErrorInvalidValue;
+    uint64_t* tabs = (uint64_t*)work;
+    const int64_t NB = (N + 63) / 64;
+    hipLaunchKernelGGL(k_block_tables, dim3((unsigned)((NB + 3) / 4)), dim3(256), 0, st, coords, N, tabs);
+    // row blocks per tile: the tallest (up to 16 x 4) that leaves at least
+    // 2048 tiles, so the tables are loaded once per many rows
+    constexpr int KB = kLink2dKB;
+    const int64_t nct = (W + KB - 1) / KB;
+    int RB = 16;
+    while (RB > 1 && ((NB + 4 * RB - 1) / (4 * RB)) * nct < 2048) RB >>= 1;
+    const int64_t nrt = (NB + 4 * RB - 1) / (4 * RB);
+    if (nrt * nct > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_link2d<KB>), dim3((unsigned)(nrt * nct)), dim3(256), 0, st, coords, N, bits, W,
+                       (const uint64_t*)tabs, nrt, RB);
+    return hipGetLastError();
+  }
   if (d == kLinkDeSitter) return launch_d<3>(N, coords, bits, W, st);
   return launch_d<4>(N, coords, bits, W, st);
 }

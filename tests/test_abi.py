@@ -59,10 +59,19 @@ def test_row_words(lib):
 
 def test_argument_errors_need_no_device(lib):
     with pytest.raises(lib.CsError) as e:
-        lib.cs_link_dev(3, 10, 0, 0, 4, None)
+        lib.cs_link_dev(3, 10, 0, 0, 4, None, 0, None)
     assert e.value.status == lib._binding.CS_EINVAL
     with pytest.raises(lib.CsError) as e:
-        lib.cs_link_dev(2, 100, 1, 1, 3, None)          # stride too small
+        lib.cs_link_dev(2, 100, 1, 1, 3, 1, 1 << 20, None)   # stride too small
+    assert e.value.status == lib._binding.CS_EINVAL
+    need = lib.cs_link_workspace_bytes(2, 100)
+    assert need == 2 * 2112                               # two blocks of 64 labels
+    assert lib.cs_link_workspace_bytes(4, 100) == 0
+    with pytest.raises(lib.CsError) as e:
+        lib.cs_link_dev(2, 100, 1, 1, 4, None, 0, None)      # 2D without its tables
+    assert e.value.status == lib._binding.CS_EINVAL
+    with pytest.raises(lib.CsError) as e:
+        lib.cs_link_dev(2, 100, 1, 1, 4, 1, need - 8, None)  # workspace too small
     assert e.value.status == lib._binding.CS_EINVAL
     with pytest.raises(lib.CsError) as e:
         lib.cs_count_dev(1, 100, 4, 2, 1, 1, 0, None)   # kmax < 3

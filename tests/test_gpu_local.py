@@ -144,7 +144,9 @@ def test_local_device_tier(cs):
     coords = torch.from_numpy(oc).to("cuda:0")
     bits = torch.zeros((N, W + 8), dtype=torch.int64, device="cuda:0")
     stream = torch.cuda.current_stream().cuda_stream
-    cs.cs_link_dev(2, N, coords.data_ptr(), bits.data_ptr(), W + 8, stream)
+    lw = cs.cs_link_workspace_bytes(2, N)
+    lwork = torch.empty(((lw + 7) // 8,), dtype=torch.int64, device="cuda:0")
+    cs.cs_link_dev(2, N, coords.data_ptr(), bits.data_ptr(), W + 8, lwork.data_ptr(), lw, stream)
     h, oR = expect(oracle.link(2, oc), N)
     wb0 = cs.cs_count_local_workspace_bytes(N)
     assert wb0 == 64 * ((N + 63) // 64)

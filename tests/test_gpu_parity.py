@@ -224,18 +224,25 @@ def test_validation_rejects_bad_matrices(cs, ctx):
 
 
 # ------------------------------------------------------------- device tier
-def test_device_pointer_tier_with_torch(cs):
+@pytest.mark.parametrize("d", [2, 4])
+def test_device_pointer_tier_with_torch(cs, d):
+    """cs_link_dev and cs_count_dev on torch-owned memory (row stride wider
+    than W; 2D with its link tables in a caller workspace): the oracle's
+    matrix, zero words past W, and its counts."""
     import torch
-    say("case device tier")
-    d, N, seed = 4, 1000, 51
+    say("case device tier d=%d" % d)
+    N, seed = 1000, 51
     oc, _, _ = oracle.sprinkle(d, N, seed)
     W = cs.cs_row_words(N)
     coords = torch.from_numpy(oc).to("cuda:0")
-    bits = torch.zeros((N, W + 4), dtype=torch.int64, device="cuda:0")   # wider stride
+    bits = torch.full((N, W + 4), -1, dtype=torch.int64, device="cuda:0")   # wider stride
     stats = torch.zeros(6, dtype=torch.int64, device="cuda:0")
     work = torch.zeros(cs.cs_count_workspace_bytes(N, 3) // 8, dtype=torch.int64, device="cuda:0")
+    lw = cs.cs_link_workspace_bytes(d, N)
+    assert lw == (2112 * ((N + 63) // 64) if d == 2 else 0)
+    lwork = torch.full((max(lw, 8) // 8,), -1, dtype=torch.int64, device="cuda:0")
     stream = torch.cuda.current_stream().cuda_stream
-    cs.cs_link_dev(d, N, coords.data_ptr(), bits.data_ptr(), W + 4, stream)
+    cs.cs_link_dev(d, N, coords.data_ptr(), bits.data_ptr(), W + 4, lwork.data_ptr() if lw else None, lw, stream)
     cs.cs_count_dev(bits.data_ptr(), N, W + 4, 3, stats.data_ptr(), work.data_ptr(), 0, stream)
     torch.cuda.synchronize()
     ob = oracle.link(d, oc)
