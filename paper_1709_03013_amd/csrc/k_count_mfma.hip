@@ -155,7 +155,11 @@ __device__ __forceinline__ uint32_t acc_count(int x) { return (uint32_t)x >> 6; 
 // of row j).  In a diagonal tile the bits of rows i >= j are cleared first,
 // so every test below is a plain bit test.  FULL bins every size m <= kmax:
 // sizes below kLdsBins in the workgroup's LDS bins (lds_hist, zeroed), larger
-// ones straight into the row-block stats.  Its loop over the 16 elements of
+// ones straight into the row-block stats.  rel: where the caller kept, in
+// LDS, the 16 bytes each lane read of its B rows in the tile's first chunk
+// (16 bytes per lane and B tile; the word of rows I0 + 32a is word
+// wl0 + a/2 of that chunk), else the relation words are read from memory.
+// Its loop over the 16 elements of
 // a 32x32 tile is not unrolled: one element's temporaries at a time keep the
 // kernel within its registers.
 template <class Sh, bool FULL, typename Acc>
@@ -163,11 +167,13 @@ __device__ __forceinline__ void mfma_epilogue(const Acc (&acc)[Sh::TM][Sh::TN],
                                               const uint64_t* __restrict__ bits, int64_t N,
                                               int64_t W, int64_t BI, int64_t BJ, int64_t I0,
                                               int64_t J0, int kmax,
-                                              uint64_t* __restrict__ rb_stats, uint32_t* lds_hist) {
+                                              uint64_t* __restrict__ rb_stats, uint32_t* lds_hist,
+                                              const char* rel = nullptr, int wl0 = 0) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int r32 = lane & 31, g = lane >> 5;
   uint32_t cnt[4] = {0, 0, 0, 0};
+  uint32_t pk[2] = {0, 0};
   uint32_t nrel = 0;
   // a lane sums at most 16*TM*TN <= 128 interval sizes m <= N - 2; a matrix
   // of 2^21 or more elements needs at least 2^39 bytes, more than a device
@@ -181,7 +187,16 @@ __device__ __forceinline__ void mfma_epilogue(const Acc (&acc)[Sh::TM][Sh::TN],
 #pragma unroll
     for (int a = 0; a < Sh::TM; ++a) {
       const int64_t ibase = I0 + 32 * a;
-      const uint64_t rw = j < N ? bits[j * W + (ibase >> 6)] : 0ull;
+      uint64_t rw = 0ull;
+      if (j < N) {
+        if (rel) {
+          // word wl of the tile's first chunk, kept by the lanes with g = wl / 2
+          const int wl = wl0 + (a >> 1);
+          rw = *(const uint64_t*)(rel + (b * 64 + r32 + 32 * (wl >> 1)) * 16 + 8 * (wl & 1));
+        } else {
+          rw = bits[j * W + (ibase >> 6)];
+        }
+      }
       uint32_t r = (uint32_t)(rw >> (ibase & 63));
       if (BI == BJ) {
         const int64_t lim = j - ibase;  // rows ri < lim have i < j
@@ -205,15 +220,23 @@ __device__ __forceinline__ void mfma_epilogue(const Acc (&acc)[Sh::TM][Sh::TN],
           }
         }
       } else {
+        // R: one bit count of the lane's 16 relation bits of the tile.
+        // N_0..N_3: 7-bit fields of pk (bits 0, 7, 14, 21; sizes >= 4 go to
+        // bits 28.. and their carries leave the word), each half of the
+        // lane's tiles (<= 64 pairs) in its own word, so no field overflows.
+        nrel = bcnt_acc(r & (0x0F0F0F0Fu << (4 * g)), nrel);
+        const int h = (b * Sh::TM + a) < (Sh::TM * Sh::TN) / 2 ? 0 : 1;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           const int ri = 8 * (v >> 2) + 4 * g + (v & 3);
-          const bool valid = (r >> ri) & 1u;
+          const uint32_t valid = (r >> ri) & 1u;
           const uint32_t m = acc_count(acc[a][b][v]);
-          nrel += valid ? 1u : 0u;
-          lsum += valid ? m : 0u;
-#pragma unroll
-          for (int k = 0; k < 4; ++k) cnt[k] += (valid && m == (uint32_t)k) ? 1u : 0u;
+          if constexpr (std::is_same<Acc, v16f>::value)
+            lsum += __umul24(valid, m);  // fp4 path: m < 2^24
+          else
+            lsum += valid ? m : 0u;
+          const uint32_t sz = m < 4u ? m : 4u;
+          pk[h] += valid << (7u * sz);
         }
       }
     }
@@ -222,7 +245,7 @@ __device__ __forceinline__ void mfma_epilogue(const Acc (&acc)[Sh::TM][Sh::TN],
   const uint64_t summ = wave_sum_u64(lsum);
   if constexpr (!FULL) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) cnt[k] = wave_sum_u32(cnt[k]);
+    for (int k = 0; k < 4; ++k) cnt[k] = wave_sum_u32(((pk[0] >> (7 * k)) & 127u) + ((pk[1] >> (7 * k)) & 127u));
     if (lane < 4) {
       const uint32_t v = lane == 0 ? cnt[0] : lane == 1 ? cnt[1] : lane == 2 ? cnt[2] : cnt[3];
       if (v) atomicAdd((unsigned long long*)&st[lane], (unsigned long long)v);
@@ -457,25 +480,152 @@ __global__ __launch_bounds__(Big::Threads, 1) void k_count_mfma_lds(
 // Batched, persistent: each workgroup takes (set, BI, BJ) items of its tile
 // shape, sorted longest first, in snake order until none is left.  fp4 is
 // exact for the batch's N <= CS_BATCH_NMAX < 2^24.
+//
+// The chunks of all the workgroup's items form one stream: the LDS-DMA loads
+// run kStages-1 chunks ahead of the contraction across item boundaries, so
+// an item's first chunks are already in LDS when the previous item's
+// epilogue runs, and the epilogue reads no memory (its relation words come
+// from the item's first chunk in LDS).  The wait before chunk p is the same as in
+// a single tile: at most L*(kStages-2) of the wave's vector-memory operations
+// outstanding; the epilogue's loads and atomics are vector-memory
+// operations too, issued after the loads they follow, and operations
+// complete in issue order, so they can only make a wait longer.  At the end
+// of the stream the last chunk is loaded again into a stage nobody reads
+// (as the single-tile prologue does), so the count of loads in flight stays
+// the same.
 template <class Sh>
 __device__ __forceinline__ void batch_count_mfma(const BatchDev& b, const uint64_t* items, int64_t n,
                                                  char* smem) {
-  for (int64_t k = 0;; ++k) {
-    const int64_t it = snake_item(k);
-    if (it >= n) break;
-    // The previous item's last stage may still be read by a slower wave;
-    // the next item's prologue refills stages 0..S-2 straight away.
-    if (k > 0) __syncthreads();
+  constexpr int S = kStages;
+  constexpr int BT = Sh::BT, TM = Sh::TM, TN = Sh::TN, WN = Sh::WN, L = Sh::L;
+  static_assert(L * Sh::Threads == 4 * BT && S >= 2 && L * (S - 2) <= 63, "bad stage shape");
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int r32 = lane & 31, g = lane >> 5;
+
+  uint32_t aoff[TM], boff[TN];
+#pragma unroll
+  for (int t = 0; t < TM; ++t) aoff[t] = 16u * stage_slot((wave / WN) * (32 * TM) + 32 * t + r32, g);
+#pragma unroll
+  for (int t = 0; t < TN; ++t) boff[t] = 16u * stage_slot(BT + (wave % WN) * (32 * TN) + 32 * t + r32, g);
+
+  typedef __attribute__((address_space(3))) void* lds_ptr;
+  typedef __attribute__((address_space(1))) const void* global_ptr;
+
+  // issue cursor: item round ki, next chunk ci of that item (last chunk ci1)
+  int64_t ki = 0, ci = 0, ci1 = 0;
+  bool iend = false;
+  const char* gbase[L];
+  uint32_t goff[L];
+  auto issue_item = [&]() -> bool {
+    const int64_t it = snake_item(ki);
+    if (it >= n) return false;
     int64_t set, BI, BJ;
     unpack_item(items[it], &set, &BI, &BJ);
     const BatchSet bs = b.sets[set];
-    mfma_tile_lds<Sh, false, true>(b.bits + bs.bits_off, bs.N, bs.W, BI, BJ, 3,
-                                   b.stats + bs.stats_off, nullptr, smem);
+    const uint64_t* bits = b.bits + bs.bits_off;
+    // DMA slot geometry as in mfma_tile_lds
+#pragma unroll
+    for (int p = 0; p < L; ++p) {
+      const int slot0 = (wave * L + p) * 64;  // uniform
+      const int slot = slot0 + lane;
+      const int r = (slot >> 1) & (BT - 1);
+      const int half = (slot & 1) ^ stage_swz(r);
+      const int64_t blk = slot0 >= 2 * BT ? BJ : BI;
+      gbase[p] = (const char*)(bits + blk * BT * bs.W);
+      const bool valid = blk * BT + r < bs.N;
+      goff[p] = (uint32_t)((valid ? (int64_t)r * bs.W * 8 : 0) + 16 * half);
+    }
+    ci = BI * BT / 256;
+    ci1 = (BJ * BT + BT - 1) / 256;
+    return true;
+  };
+  auto issue_next = [&](int st) {
+#pragma unroll
+    for (int p = 0; p < L; ++p)
+      __builtin_amdgcn_global_load_lds((global_ptr)(gbase[p] + ci * 32 + goff[p]),
+                                       (lds_ptr)(smem + st * Sh::StageBytes + (wave * L + p) * 1024),
+                                       16, 0, 0);
+    if (ci < ci1) {
+      ++ci;
+    } else if (!iend) {
+      ++ki;
+      if (!issue_item()) iend = true;  // the stream's last chunk is issued again from now on
+    }
+  };
+
+  if (!issue_item()) return;  // no item for this workgroup (uniform)
+#pragma unroll
+  for (int k = 0; k < S - 1; ++k) issue_next(k);
+
+  using Acc = v16f;
+  int st = 0;
+  for (int64_t kc = 0;; ++kc) {
+    const int64_t it = snake_item(kc);
+    if (it >= n) break;
+    int64_t set, BI, BJ;
+    unpack_item(items[it], &set, &BI, &BJ);
+    const BatchSet bs = b.sets[set];
+    const uint64_t* bits = b.bits + bs.bits_off;
+    const int64_t I0 = BI * BT + (wave / WN) * (32 * TM);
+    const int64_t J0 = BJ * BT + (wave % WN) * (32 * TN);
+    Acc acc[TM][TN];
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int bb = 0; bb < TN; ++bb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[a][bb][v] = 0;
+    const int64_t c0 = BI * BT / 256, c1 = (BJ * BT + BT - 1) / 256;
+    // The epilogue's relation words (bit i of row j) lie in the item's first
+    // chunk of the B rows: taken from LDS there instead of from memory, whose
+    // loads would wait behind the next item's chunks in flight.
+    // Kept in this wave's slice of LDS past the stages until the epilogue.
+    char* rel = smem + S * Sh::StageBytes + wave * (64 * TN * 16);
+    // one chunk; the item's first also keeps the relation words in LDS
+    auto step = [&](int64_t c, auto first) {
+      asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(L * (S - 2)) : "memory");
+      issue_next(st == 0 ? S - 1 : st - 1);
+      const char* sb = smem + st * Sh::StageBytes;
+      uint32_t xa[TM][4], xb[TN][4];
+#pragma unroll
+      for (int t = 0; t < TM; ++t) {
+        const uint4 v = *(const uint4*)(sb + aoff[t]);
+        xa[t][0] = v.x; xa[t][1] = v.y; xa[t][2] = v.z; xa[t][3] = v.w;
+      }
+#pragma unroll
+      for (int t = 0; t < TN; ++t) {
+        const uint4 v = *(const uint4*)(sb + boff[t]);
+        xb[t][0] = v.x; xb[t][1] = v.y; xb[t][2] = v.z; xb[t][3] = v.w;
+      }
+      if constexpr (decltype(first)::value) {
+        // keep this lane's 16 bytes of each B row (words 4c0 + 2g and
+        // 4c0 + 2g + 1) for the epilogue
+#pragma unroll
+        for (int t = 0; t < TN; ++t)
+          *(uint4*)(rel + (t * 64 + lane) * 16) = make_uint4(xb[t][0], xb[t][1], xb[t][2], xb[t][3]);
+      }
+      mfma_chunk<Sh, true>(acc, xa, xb, I0, J0, c, c == c0, c == c1);
+      st = st == S - 1 ? 0 : st + 1;
+    };
+    step(c0, std::true_type{});
+    for (int64_t c = c0 + 1; c <= c1; ++c) step(c, std::false_type{});
+    mfma_epilogue<Sh, false>(acc, bits, bs.N, bs.W, BI, BJ, I0, J0, 3, b.stats + bs.stats_off, nullptr, rel,
+                             (int)((I0 >> 6) - 4 * c0));
   }
+  // No LDS DMA may still be writing when the workgroup ends.
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
+// LDS of a batched count workgroup: the stages, then each wave's relation words.
+template <class Sh>
+constexpr int batch_lds_bytes() {
+  return kStages * Sh::StageBytes + (Sh::Threads / 64) * 64 * Sh::TN * 16;
 }
 
 __global__ __launch_bounds__(Big::Threads, 1) void k_batch_count_mfma(BatchDev b) {
-  extern __shared__ __align__(16) char smem[];  // kStages stages
+  extern __shared__ __align__(16) char smem[];  // batch_lds_bytes<Big>()
   batch_count_mfma<Big>(b, b.mfma_items, b.n_mfma, smem);
 }
 
@@ -483,7 +633,7 @@ __global__ __launch_bounds__(Big::Threads, 1) void k_batch_count_mfma(BatchDev b
 // workgroup's prologue and epilogue overlap the others' matrix-core work.
 __global__ __launch_bounds__(Small::Threads) __attribute__((amdgpu_waves_per_eu(3, 8))) void
 k_batch_count_mfma128(BatchDev b) {
-  extern __shared__ __align__(16) char smem[];  // kStages stages
+  extern __shared__ __align__(16) char smem[];  // batch_lds_bytes<Small>()
   batch_count_mfma<Small>(b, b.mfma128_items, b.n_mfma128, smem);
 }
 
@@ -525,7 +675,10 @@ hipError_t init_count_mfma() {
   const int stages = kStages * Big::StageBytes;
   const int full = stages + kLdsBins * (int)sizeof(uint32_t);
   hipError_t e = hipFuncSetAttribute((const void*)k_batch_count_mfma,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, stages);
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, batch_lds_bytes<Big>());
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_batch_count_mfma128, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            batch_lds_bytes<Small>());
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_count_mfma_lds<false, false>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, stages);
@@ -544,14 +697,14 @@ hipError_t init_count_mfma() {
 hipError_t launch_batch_count_mfma(const BatchDev& b, int grid, hipStream_t st) {
   if (b.n_mfma <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_batch_count_mfma, dim3((unsigned)grid), dim3(Big::Threads),
-                     (size_t)kStages * Big::StageBytes, st, b);
+                     (size_t)batch_lds_bytes<Big>(), st, b);
   return hipGetLastError();
 }
 
 hipError_t launch_batch_count_mfma128(const BatchDev& b, int grid, hipStream_t st) {
   if (b.n_mfma128 <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_batch_count_mfma128, dim3((unsigned)grid), dim3(Small::Threads),
-                     (size_t)kStages * Small::StageBytes, st, b);
+                     (size_t)batch_lds_bytes<Small>(), st, b);
   return hipGetLastError();
 }
 
@@ -562,10 +715,10 @@ int batch_count_max_blocks(int kind) {
   hipError_t e = hipSuccess;
   if (kind == 2)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_batch_count_mfma,
-                                                     Big::Threads, (size_t)kStages * Big::StageBytes);
+                                                     Big::Threads, (size_t)batch_lds_bytes<Big>());
   else
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_batch_count_mfma128,
-                                                     Small::Threads, (size_t)kStages * Small::StageBytes);
+                                                     Small::Threads, (size_t)batch_lds_bytes<Small>());
   return e == hipSuccess && n > 0 ? n : 1;
 }
 
