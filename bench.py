@@ -480,6 +480,13 @@ def served(cs, nreq=10000, slots=4, budget_gib=32.0, load=0.7):
         cal_n = min(1500, nreq)
         t_cal, _, _ = drive(reqs[:cal_n], None, set())
         sat = cal_n / t_cal
+        # the burst's counting work (2*C(N,3) per request) per second of the
+        # burst, against the fp4 matrix-core peak
+        cal_ops = sum(2.0 * math.comb(N, 3) for _, N, _ in reqs[:cal_n])
+        sat_roof = with_frac({"bound": "mfma", "achieved": cal_ops / t_cal / 1e12,
+                              "peak": PEAK["fp4_mfma_flops"] / 1e12, "unit": "TFLOP/s",
+                              "work": "sum of 2*C(N,3) over the %d burst requests per second of the burst "
+                                      "(whole requests: sprinkle, sort, link, count)" % cal_n})
         log("served (%g GiB): saturated %.0f actions/s on a burst of %d" % (budget_gib, sat, cal_n))
         rate = load * sat
         gaps = np.array([a for a, *_ in plan])
@@ -488,7 +495,7 @@ def served(cs, nreq=10000, slots=4, budget_gib=32.0, load=0.7):
         ok = all(kept[q]["n"] == o["n"] and kept[q]["R"] == o["R"] and kept[q]["summ"] == o["summ"]
                  and kept[q]["S"] == float.fromhex(o["S"]) for q, o in check.items())
         return {"requests": nreq, "slots": slots, "hbm_budget_gib": budget_gib,
-                "saturated_actions_per_s": sat, "offered_rate_per_s": rate,
+                "saturated_actions_per_s": sat, "saturated_roofline": sat_roof, "offered_rate_per_s": rate,
                 "actions_per_s": nreq / t_run, "p50_ms": float(np.percentile(lat, 50) * 1e3),
                 "p99_ms": float(np.percentile(lat, 99) * 1e3), "wall_s": t_run,
                 "checked_against_oracle": len(check), "equals_oracle": ok if check else None}

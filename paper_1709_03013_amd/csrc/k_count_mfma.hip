@@ -493,10 +493,9 @@ __global__ __launch_bounds__(Big::Threads, 1) void k_count_mfma_lds(
 // of the stream the last chunk is loaded again into a stage nobody reads
 // (as the single-tile prologue does), so the count of loads in flight stays
 // the same.
-template <class Sh>
+template <class Sh, int S>
 __device__ __forceinline__ void batch_count_mfma(const BatchDev& b, const uint64_t* items, int64_t n,
                                                  char* smem) {
-  constexpr int S = kStages;
   constexpr int BT = Sh::BT, TM = Sh::TM, TN = Sh::TN, WN = Sh::WN, L = Sh::L;
   static_assert(L * Sh::Threads == 4 * BT && S >= 2 && L * (S - 2) <= 63, "bad stage shape");
   const int tid = threadIdx.x;
@@ -618,23 +617,29 @@ __device__ __forceinline__ void batch_count_mfma(const BatchDev& b, const uint64
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
-// LDS of a batched count workgroup: the stages, then each wave's relation words.
-template <class Sh>
+// LDS of a batched count workgroup: S stages, then each wave's relation words.
+// Stages of the batched kernels (4/4, 4/5, 5/6 and 6/8 for the 256- and
+// 128-row tiles gave the same 512-set ensemble time within 5%).
+constexpr int kBatchStagesBig = 4;
+constexpr int kBatchStagesSmall = 4;
+template <class Sh, int S>
 constexpr int batch_lds_bytes() {
-  return kStages * Sh::StageBytes + (Sh::Threads / 64) * 64 * Sh::TN * 16;
+  return S * Sh::StageBytes + (Sh::Threads / 64) * 64 * Sh::TN * 16;
 }
+constexpr int kBatchLdsBig = batch_lds_bytes<Big, kBatchStagesBig>();
+constexpr int kBatchLdsSmall = batch_lds_bytes<Small, kBatchStagesSmall>();
 
 __global__ __launch_bounds__(Big::Threads, 1) void k_batch_count_mfma(BatchDev b) {
-  extern __shared__ __align__(16) char smem[];  // batch_lds_bytes<Big>()
-  batch_count_mfma<Big>(b, b.mfma_items, b.n_mfma, smem);
+  extern __shared__ __align__(16) char smem[];  // kBatchLdsBig bytes
+  batch_count_mfma<Big, kBatchStagesBig>(b, b.mfma_items, b.n_mfma, smem);
 }
 
 // 128-row tiles: at least 3 waves per SIMD (three workgroups per CU), so one
 // workgroup's prologue and epilogue overlap the others' matrix-core work.
 __global__ __launch_bounds__(Small::Threads) __attribute__((amdgpu_waves_per_eu(3, 8))) void
 k_batch_count_mfma128(BatchDev b) {
-  extern __shared__ __align__(16) char smem[];  // batch_lds_bytes<Small>()
-  batch_count_mfma<Small>(b, b.mfma128_items, b.n_mfma128, smem);
+  extern __shared__ __align__(16) char smem[];  // kBatchLdsSmall bytes
+  batch_count_mfma<Small, kBatchStagesSmall>(b, b.mfma128_items, b.n_mfma128, smem);
 }
 
 template <bool FP4>
@@ -675,10 +680,10 @@ hipError_t init_count_mfma() {
   const int stages = kStages * Big::StageBytes;
   const int full = stages + kLdsBins * (int)sizeof(uint32_t);
   hipError_t e = hipFuncSetAttribute((const void*)k_batch_count_mfma,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, batch_lds_bytes<Big>());
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, kBatchLdsBig);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_batch_count_mfma128, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            batch_lds_bytes<Small>());
+                            kBatchLdsSmall);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_count_mfma_lds<false, false>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, stages);
@@ -697,14 +702,14 @@ hipError_t init_count_mfma() {
 hipError_t launch_batch_count_mfma(const BatchDev& b, int grid, hipStream_t st) {
   if (b.n_mfma <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_batch_count_mfma, dim3((unsigned)grid), dim3(Big::Threads),
-                     (size_t)batch_lds_bytes<Big>(), st, b);
+                     (size_t)kBatchLdsBig, st, b);
   return hipGetLastError();
 }
 
 hipError_t launch_batch_count_mfma128(const BatchDev& b, int grid, hipStream_t st) {
   if (b.n_mfma128 <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_batch_count_mfma128, dim3((unsigned)grid), dim3(Small::Threads),
-                     (size_t)batch_lds_bytes<Small>(), st, b);
+                     (size_t)kBatchLdsSmall, st, b);
   return hipGetLastError();
 }
 
@@ -715,10 +720,10 @@ int batch_count_max_blocks(int kind) {
   hipError_t e = hipSuccess;
   if (kind == 2)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_batch_count_mfma,
-                                                     Big::Threads, (size_t)batch_lds_bytes<Big>());
+                                                     Big::Threads, (size_t)kBatchLdsBig);
   else
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_batch_count_mfma128,
-                                                     Small::Threads, (size_t)batch_lds_bytes<Small>());
+                                                     Small::Threads, (size_t)kBatchLdsSmall);
   return e == hipSuccess && n > 0 ? n : 1;
 }
 

@@ -207,11 +207,15 @@ __device__ __forceinline__ bool rec_less(const SortRec& a, const SortRec& b) {
   return a.idx < b.idx;
 }
 
-// Bitonic sort of n <= kSortTile records at base, in LDS, by 1024 threads.
+// Bitonic sort of n <= kSortTile records at base, in LDS, by 1024 threads,
+// over the smallest power of two P >= n (padded with records above every
+// key): a tile of a small set sorts P slots, not kSortTile.
 __device__ __forceinline__ void tile_sort_body(SortRec* __restrict__ base, int64_t n,
                                                SortRec* s) {
   const int tid = threadIdx.x;
-  for (int q = tid; q < kSortTile; q += 1024) {
+  int P = 2;
+  while (P < n) P <<= 1;
+  for (int q = tid; q < P; q += 1024) {
     if (q < n) {
       s[q] = base[q];
     } else {
@@ -221,9 +225,9 @@ __device__ __forceinline__ void tile_sort_body(SortRec* __restrict__ base, int64
     }
   }
   __syncthreads();
-  for (int k = 2; k <= kSortTile; k <<= 1) {
+  for (int k = 2; k <= P; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int q = tid; q < kSortTile; q += 1024) {
+      for (int q = tid; q < P; q += 1024) {
         const int p = q ^ j;
         if (p > q) {
           const bool up = (q & k) == 0;
