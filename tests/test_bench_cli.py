@@ -23,6 +23,9 @@ def test_traffic_keyed_by_sources():
     try:
         bench.TRAFFIC[k] = {"sources": digest, "bytes": 123}
         assert bench.traffic_bytes(k) == 123
+        # counted on the 2D N = 131072 workload only
+        assert bench.traffic_bytes(k, 16384, 4) is None
+        assert bench.traffic_bytes(k, 1024, 2) is None
         bench.TRAFFIC[k] = {"sources": "0" * 16, "bytes": 123}
         assert bench.traffic_bytes(k) is None
         bench.TRAFFIC.pop(k)
