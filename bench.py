@@ -25,8 +25,8 @@ Also reported on the same line:
   * desitter: ten (1+1) de Sitter slabs of 2^15 elements (eta0 = 0.5), the
     smeared action at eps = 2^-6 against 4 pi tan(eta0), and a sweep over N
     (40 graphs per size, 20 at 2^17);
-  * served: 10,000 queued requests (N log-uniform in [512, 32768]) with
-    Poisson arrivals at 0.7x the saturated rate, p50/p99 latency and
+  * served: 10,000 queued requests (N log-uniform in [512, 32768]) on 8 queue
+    slots, Poisson arrivals at 0.7x the saturated rate, p50/p99 latency and
     actions/s, under a 32 GiB and a 1 GiB budget; every 50th result checked
     against the stored oracle results;
   * cpu_baseline: the CPU oracle's counting rate on fixed row samples of the
@@ -440,7 +440,7 @@ def desitter(cs, ctx, N=32768, graphs=10, eta0=0.5, eps=2.0**-6,
             "S_EH": 4 * math.pi * math.tan(eta0), "graphs_per_s": graphs / t, "by_N": by_n}
 
 
-def served(cs, nreq=10000, slots=4, budget_gib=32.0, load=0.7):
+def served(cs, nreq=10000, slots=8, budget_gib=32.0, load=0.7):
     """Served stream: requests with Poisson arrivals (N log-uniform in
     [512, 32768], d in {2, 4}).  After an untimed warm-up (one request per
     dimension and size bucket, which lets the path tuner time its kernels),
@@ -541,6 +541,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-only", action="store_true",
                     help="only the served stream (32 GiB budget), printed as one JSON line")
+    ap.add_argument("--serve-slots", type=int, default=8, help="queue slots (streams) of the served stream")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -565,7 +566,7 @@ def main():
 
     if a.serve_only:
         torch.cuda.init()
-        print(json.dumps(served(cs, a.serve_requests, budget_gib=32.0)))
+        print(json.dumps(served(cs, a.serve_requests, slots=a.serve_slots, budget_gib=32.0)))
         return
 
     torch.cuda.init()
@@ -635,8 +636,8 @@ def main():
     dsx = None if a.no_desitter else desitter(cs, ctx)
     srv = None
     if not a.no_serve:
-        srv = {"unbound_32gib": served(cs, a.serve_requests, budget_gib=32.0),
-               "bound_1gib": served(cs, a.serve_requests, budget_gib=1.0)}
+        srv = {"unbound_32gib": served(cs, a.serve_requests, slots=a.serve_slots, budget_gib=32.0),
+               "bound_1gib": served(cs, a.serve_requests, slots=a.serve_slots, budget_gib=1.0)}
     cs.cs_destroy(ctx)
     cpu = None if a.no_cpu else cpu_baseline()
 

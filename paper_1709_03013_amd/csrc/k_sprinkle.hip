@@ -207,41 +207,71 @@ __device__ __forceinline__ bool rec_less(const SortRec& a, const SortRec& b) {
   return a.idx < b.idx;
 }
 
-// Bitonic sort of n <= kSortTile records at base, in LDS, by 1024 threads,
-// over the smallest power of two P >= n (padded with records above every
-// key): a tile of a small set sorts P slots, not kSortTile.
+// One record of lane ^ m of the wave.
+__device__ __forceinline__ SortRec shfl_rec(const SortRec& r, int m) {
+  SortRec o;
+  o.k1 = (uint64_t)__shfl_xor((long long)r.k1, m, 64);
+  o.k2 = (uint64_t)__shfl_xor((long long)r.k2, m, 64);
+  o.idx = (uint64_t)__shfl_xor((long long)r.idx, m, 64);
+  return o;
+}
+
+// The smaller (lo) or larger of a and b.
+__device__ __forceinline__ SortRec pick(const SortRec& a, const SortRec& b, bool lo) {
+  return rec_less(b, a) == lo ? b : a;
+}
+
+// Bitonic sort of n <= kSortTile records at base by 1024 threads, over the
+// smallest power of two P >= n (padded with records above every key).
+// Thread t holds positions 2t and 2t+1 in registers.  A compare-exchange
+// step at distance j pairs position p with p ^ j: j = 1 stays inside the
+// thread, 2 <= j <= 64 pairs lanes t and t ^ j/2 of the same wave (lane
+// shuffles, no barrier), and only j >= 128 goes through LDS (10 of the 66
+// steps of a full tile).  Position p keeps the smaller record iff it is the
+// lower of its pair exactly when its block of size k is ascending.
 __device__ __forceinline__ void tile_sort_body(SortRec* __restrict__ base, int64_t n,
                                                SortRec* s) {
-  const int tid = threadIdx.x;
+  const int t = threadIdx.x;
   int P = 2;
   while (P < n) P <<= 1;
-  for (int q = tid; q < P; q += 1024) {
-    if (q < n) {
-      s[q] = base[q];
-    } else {
-      s[q].k1 = ~0ull;
-      s[q].k2 = ~0ull;
-      s[q].idx = ~0ull;
-    }
-  }
-  __syncthreads();
+  SortRec pad;
+  pad.k1 = ~0ull;
+  pad.k2 = ~0ull;
+  pad.idx = ~0ull;
+  const int p0 = 2 * t;
+  SortRec r0 = p0 < n ? base[p0] : pad;
+  SortRec r1 = p0 + 1 < n ? base[p0 + 1] : pad;
   for (int k = 2; k <= P; k <<= 1) {
+    const bool up = (p0 & k) == 0;
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int q = tid; q < P; q += 1024) {
-        const int p = q ^ j;
-        if (p > q) {
-          const bool up = (q & k) == 0;
-          SortRec x = s[q], y = s[p];
-          if (rec_less(y, x) == up) {
-            s[q] = y;
-            s[p] = x;
-          }
+      if (j == 1) {
+        // positions p0 (lower) and p0 + 1
+        if (rec_less(r1, r0) == up) {
+          const SortRec x = r0;
+          r0 = r1;
+          r1 = x;
         }
+      } else {
+        const bool lo = ((p0 & j) == 0) == up;
+        SortRec o0, o1;
+        if (j <= 64) {
+          o0 = shfl_rec(r0, j >> 1);
+          o1 = shfl_rec(r1, j >> 1);
+        } else {
+          s[p0] = r0;
+          s[p0 + 1] = r1;
+          __syncthreads();
+          o0 = s[p0 ^ j];
+          o1 = s[(p0 + 1) ^ j];
+          __syncthreads();  // before the next step writes s
+        }
+        r0 = pick(r0, o0, lo);
+        r1 = pick(r1, o1, lo);
       }
-      __syncthreads();
     }
   }
-  for (int q = tid; q < n; q += 1024) base[q] = s[q];
+  if (p0 < n) base[p0] = r0;
+  if (p0 + 1 < n) base[p0 + 1] = r1;
 }
 
 __global__ __launch_bounds__(1024) void k_tile_sort(SortRec* __restrict__ recs,
