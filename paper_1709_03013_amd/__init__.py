@@ -7,6 +7,6 @@ binding with the same function names.  Build with
 ``python -m paper_1709_03013_amd.build``.
 """
 from ._binding import *  # noqa: F401,F403
-from ._binding import CsError, lib, exported_symbols  # noqa: F401
+from ._binding import BatchCall, CsError, lib, exported_symbols  # noqa: F401
 
-__all__ = [n for n in dir() if n.startswith("cs_")] + ["CsError", "lib", "exported_symbols"]
+__all__ = [n for n in dir() if n.startswith("cs_")] + ["BatchCall", "CsError", "lib", "exported_symbols"]

@@ -343,12 +343,29 @@ def make_reqs(plan):
     return arr
 
 
+class BatchCall:
+    """The marshalled arguments of cs_batch_run for one list of (d, N, seed):
+    the request and result arrays are built once, so repeated calls pass
+    straight to the library (run), and the results are converted on demand
+    (results)."""
+
+    def __init__(self, plan):
+        plan = list(plan)
+        self.n = len(plan)
+        self.reqs = make_reqs(plan)
+        self.out = (cs_result * max(self.n, 1))()
+
+    def run(self, ctx: int) -> None:
+        _check(lib().cs_batch_run(ctx, self.n, self.reqs, self.out))
+
+    def results(self):
+        return [self.out[k].as_dict() for k in range(self.n)]
+
+
 def cs_batch_run(ctx: int, plan):
-    plan = list(plan)
-    reqs = make_reqs(plan)
-    out = (cs_result * max(len(plan), 1))()
-    _check(lib().cs_batch_run(ctx, len(plan), reqs, out))
-    return [out[k].as_dict() for k in range(len(plan))]
+    call = BatchCall(plan)
+    call.run(ctx)
+    return call.results()
 
 
 def cs_batch_last_info(ctx: int) -> dict:

@@ -46,6 +46,18 @@ MIXED = [(2, 0, 5), (2, 1, 6), (4, 2, 7), (2, 63, 8), (4, 65, 9), (2, 300, 10), 
          (2, 16384, 18)]
 
 
+def test_batch_call_reused_arrays_match_cs_batch_run(cs, ctx):
+    # BatchCall marshals once and calls the library repeatedly: every call
+    # overwrites the same result array with the same results
+    say("case batch call reuse")
+    plan = MIXED[5:10]
+    ref = cs.cs_batch_run(ctx, plan)
+    call = cs.BatchCall(plan)
+    for _ in range(3):
+        call.run(ctx)
+        assert call.results() == ref
+
+
 def test_batch_mixed_sizes_match_per_set_and_oracle(cs, ctx):
     say("case batch mixed")
     res = cs.cs_batch_run(ctx, MIXED)
