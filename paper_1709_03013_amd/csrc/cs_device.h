@@ -60,6 +60,22 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
   return v;
 }
 
+// Sum over the 64 lanes as a wave-uniform value, without LDS: DPP row
+// shifts by 1, 2, 4, 8 leave each row of 16 lanes with its prefix sums (lane
+// 15 of the row holds the row's total), row_bcast:15 adds row 0's total to
+// row 1 and row 2's to row 3, row_bcast:31 adds lane 31 (rows 0-1) to rows
+// 2-3, and lane 63 ends with the total.  Lanes a shift or broadcast does not
+// reach add 0.
+__device__ __forceinline__ uint32_t wave_total_u32(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);  // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);  // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);  // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);  // row_shr:8
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 // popcount(x) + c as one v_bcnt_u32_b32, so accumulation stays a chain of
 // bcnt ops instead of being regrouped into extra adds.
 __device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t c) {

@@ -58,20 +58,13 @@ using Big = Shape<256, 2, 4>;
 using Small = Shape<128, 2, 2>;
 constexpr int kStages = 4;
 
-// Columns of word w strictly above label i.
-__device__ __forceinline__ uint64_t mask_above(int64_t i, int64_t w) {
-  const int64_t wi = i >> 6;
-  if (w < wi) return 0ull;
-  if (w > wi) return ~0ull;
-  return ~((2ull << (i & 63)) - 1);
-}
-
-// Columns of word w strictly below label j.
-__device__ __forceinline__ uint64_t mask_below(int64_t j, int64_t w) {
-  const int64_t wj = j >> 6;
-  if (w > wj) return 0ull;
-  if (w < wj) return ~0ull;
-  return (1ull << (j & 63)) - 1;
+// Of the 32 columns cb .. cb+31, those at or above cb + s: the shift count
+// clamped to 0..32 and one 64-bit shift, so that s >= 32 empties the word.
+// Columns above label i: s = i + 1 - cb; below label j: the complement with
+// s = j - cb.
+__device__ __forceinline__ uint32_t cols_from(int s) {
+  const int c = s < 0 ? 0 : (s > 32 ? 32 : s);
+  return (uint32_t)(0xFFFFFFFFull << c);
 }
 
 // Weighted spreading.  The k order only has to be the same for A and B; the
@@ -148,6 +141,18 @@ __device__ __forceinline__ v8i spread_fp4_wb(uint32_t D) {
 // int8: the int32 sum over products of 64).
 __device__ __forceinline__ uint32_t acc_count(float x) { return (uint32_t)x; }
 __device__ __forceinline__ uint32_t acc_count(int x) { return (uint32_t)x >> 6; }
+
+// a * b + c for a, b < 2^24, and (a << s) + c, each as one instruction.
+__device__ __forceinline__ uint32_t mad_u24(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+__device__ __forceinline__ uint32_t lshl_add(uint32_t a, uint32_t s, uint32_t c) {
+  uint32_t r;
+  asm("v_lshl_add_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(s), "v"(c));
+  return r;
+}
 
 // Epilogue of one 256x256 tile.  Lane l holds column j = J0 + 32b + l%32
 // and rows i = I0 + 32a + 8(v/4) + 4(l/32) + v%4 of tile (a, b); the
@@ -226,26 +231,35 @@ __device__ __forceinline__ void mfma_epilogue(const Acc (&acc)[Sh::TM][Sh::TN],
         // lane's tiles (<= 64 pairs) in its own word, so no field overflows.
         nrel = bcnt_acc(r & (0x0F0F0F0Fu << (4 * g)), nrel);
         const int h = (b * Sh::TM + a) < (Sh::TM * Sh::TN) / 2 ? 0 : 1;
+        const uint32_t rg = r >> (4 * g);  // element v's bit at 8(v/4) + v%4
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-          const int ri = 8 * (v >> 2) + 4 * g + (v & 3);
-          const uint32_t valid = (r >> ri) & 1u;
+          const uint32_t valid = (rg >> (8 * (v >> 2) + (v & 3))) & 1u;
           const uint32_t m = acc_count(acc[a][b][v]);
           if constexpr (std::is_same<Acc, v16f>::value)
-            lsum += __umul24(valid, m);  // fp4 path: m < 2^24
+            lsum = mad_u24(valid, m, lsum);  // fp4 path: m < 2^24
           else
             lsum += valid ? m : 0u;
           const uint32_t sz = m < 4u ? m : 4u;
-          pk[h] += valid << (7u * sz);
+          pk[h] = lshl_add(valid, 7u * sz, pk[h]);
         }
       }
     }
   }
-  nrel = wave_sum_u32(nrel);
-  const uint64_t summ = wave_sum_u64(lsum);
+  // wave totals (uniform): the sum of m in two 16-bit halves, N_0..N_3 two
+  // to a word (at most 128 pairs per lane, 8192 per wave, in 16 bits)
+  nrel = wave_total_u32(nrel);
+  const uint64_t summ =
+      (uint64_t)wave_total_u32(lsum & 0xFFFFu) + ((uint64_t)wave_total_u32(lsum >> 16) << 16);
   if constexpr (!FULL) {
+    uint32_t f[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) cnt[k] = wave_sum_u32(((pk[0] >> (7 * k)) & 127u) + ((pk[1] >> (7 * k)) & 127u));
+    for (int k = 0; k < 4; ++k) f[k] = ((pk[0] >> (7 * k)) & 127u) + ((pk[1] >> (7 * k)) & 127u);
+    const uint32_t t01 = wave_total_u32(f[0] | (f[1] << 16)), t23 = wave_total_u32(f[2] | (f[3] << 16));
+    cnt[0] = t01 & 0xFFFFu;
+    cnt[1] = t01 >> 16;
+    cnt[2] = t23 & 0xFFFFu;
+    cnt[3] = t23 >> 16;
     if (lane < 4) {
       const uint32_t v = lane == 0 ? cnt[0] : lane == 1 ? cnt[1] : lane == 2 ? cnt[2] : cnt[3];
       if (v) atomicAdd((unsigned long long*)&st[lane], (unsigned long long)v);
@@ -276,19 +290,24 @@ __device__ __forceinline__ void mfma_chunk(Acc (&acc)[Sh::TM][Sh::TN], uint32_t 
   constexpr int kTM = Sh::TM, kTN = Sh::TN;
   const int lane = threadIdx.x & 63;
   const int r32 = lane & 31, g = lane >> 5;
+  // dword q of the lane's 16 bytes holds columns cb + 32q .. cb + 32q + 31
+  // (labels and columns are below 2^24, so the differences fit an int)
+  const int cb = (int)(256 * c) + 128 * g;
   if (mask_a) {
 #pragma unroll
-    for (int t = 0; t < kTM; ++t)
+    for (int t = 0; t < kTM; ++t) {
+      const int s0 = (int)I0 + 32 * t + r32 + 1 - cb;  // columns above row i
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        xa[t][q] &= (uint32_t)(mask_above(I0 + 32 * t + r32, 4 * c + 2 * g + (q >> 1)) >> (32 * (q & 1)));
+      for (int q = 0; q < 4; ++q) xa[t][q] &= cols_from(s0 - 32 * q);
+    }
   }
   if (mask_b) {
 #pragma unroll
-    for (int t = 0; t < kTN; ++t)
+    for (int t = 0; t < kTN; ++t) {
+      const int s0 = (int)J0 + 32 * t + r32 - cb;  // columns below row j
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        xb[t][q] &= (uint32_t)(mask_below(J0 + 32 * t + r32, 4 * c + 2 * g + (q >> 1)) >> (32 * (q & 1)));
+      for (int q = 0; q < 4; ++q) xb[t][q] &= ~cols_from(s0 - 32 * q);
+    }
   }
   if constexpr (FP4) {
 #pragma unroll
