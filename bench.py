@@ -68,11 +68,11 @@ GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_reference.json")
 # after any change to them the figure no longer describes the kernel and is
 # reported as null.
 TRAFFIC = {
-    "k_count_mfma_lds<fp4>": {"bytes": 100826442773, "sources": "fb39dac5f6e32e0c"},
-    "k_count_mfma_lds<int8>": {"bytes": 117616698382, "sources": "fb39dac5f6e32e0c"},
-    "k_count_pop": {"bytes": 2541636446097, "sources": "1f59e1895a88f4ef"},
-    "k_sat_tile": {"bytes": 40494563303, "sources": "5444d35120a39881"},
-    "k_link": {"bytes": 2584446605, "sources": "07806149d17b1567"},
+    "k_count_mfma_lds<fp4>": {"bytes": 101100617970, "sources": "6b74ff102762c1b8"},
+    "k_count_mfma_lds<int8>": {"bytes": 120951557171, "sources": "6b74ff102762c1b8"},
+    "k_count_pop": {"bytes": 2541750221882, "sources": "061d0d7fb6e6543a"},
+    "k_sat_tile": {"bytes": 40493329440, "sources": "bde4881202704c01"},
+    "k_link": {"bytes": 2590436887, "sources": "07806149d17b1567"},
 }
 KERNEL_SOURCES = {
     "k_count_mfma_lds<int8>": ["k_count_mfma.hip", "cs_device.h", "cs_internal.h"],
