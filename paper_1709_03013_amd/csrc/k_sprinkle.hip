@@ -336,19 +336,23 @@ __global__ __launch_bounds__(256) void k_fill_recs(SortRec* __restrict__ recs,
 }
 
 // ---- batched ensembles ------------------------------------------------------
-// One workgroup draws one whole set.  In 4D it walks the candidates 256 at a
-// time, ranks the accepted ones with wave ballots and stops, all lanes
-// together, as soon as N are accepted: the same first N accepted candidates,
-// in candidate order, as the single-set path.
-__global__ __launch_bounds__(256) void k_batch_sprinkle(BatchDev b) {
-  __shared__ uint32_t wcnt[4];
+// One workgroup draws one whole set.  In 4D it walks the candidates
+// kBatchSprinkleThreads at a time, ranks the accepted ones with wave ballots
+// and stops, all lanes together, as soon as N are accepted: the same first N
+// accepted candidates, in candidate order, as the single-set path.  A 4D set
+// of 4096 elements needs about 31 000 candidates (the diamond fills pi/24 of
+// its bounding box), so the widest workgroup keeps the longest sets short.
+constexpr int kBatchSprinkleThreads = 1024;
+__global__ __launch_bounds__(kBatchSprinkleThreads) void k_batch_sprinkle(BatchDev b) {
+  constexpr int T = kBatchSprinkleThreads, NW = T / 64;
+  __shared__ uint32_t wcnt[NW];
   const BatchSet bs = b.sets[blockIdx.x];
   const int64_t N = bs.N;
   if (N <= 0) return;
   SortRec* recs = b.recs + bs.rec_off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (bs.d == 2) {
-    for (int64_t c = tid; c < N; c += 256) {
+    for (int64_t c = tid; c < N; c += T) {
       uint64_t r[4] = {(uint64_t)c, 0, 0, 0};
       philox10(r, bs.seed, 1);
       const uint64_t a = r[0] >> 11, bb = r[1] >> 11;
@@ -362,7 +366,7 @@ __global__ __launch_bounds__(256) void k_batch_sprinkle(BatchDev b) {
   }
   double* raw = b.raw + bs.raw_off;
   int64_t accepted = 0;
-  for (int64_t base = 0; accepted < N; base += 256) {
+  for (int64_t base = 0; accepted < N; base += T) {
     const int64_t c = base + tid;
     double xyz[4];
     uint64_t kt = 0;
@@ -373,7 +377,8 @@ __global__ __launch_bounds__(256) void k_batch_sprinkle(BatchDev b) {
     if (lane == 0) wcnt[wave] = (uint32_t)__popcll(bal);
     __syncthreads();
     uint32_t woff = 0, tot = 0;
-    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
       woff += q < wave ? wcnt[q] : 0u;
       tot += wcnt[q];
     }
@@ -501,7 +506,7 @@ hipError_t launch_sprinkle_desitter(int64_t N, uint64_t seed, double w0, double*
 
 hipError_t launch_batch_sprinkle(const BatchDev& b, hipStream_t st) {
   if (b.nsets <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_batch_sprinkle, dim3((unsigned)b.nsets), dim3(256), 0, st, b);
+  hipLaunchKernelGGL(k_batch_sprinkle, dim3((unsigned)b.nsets), dim3(kBatchSprinkleThreads), 0, st, b);
   if (b.n_sort > 0)
     hipLaunchKernelGGL(k_batch_tile_sort, dim3((unsigned)b.n_sort), dim3(1024), 0, st, b);
   if (b.n_elem > 0)
