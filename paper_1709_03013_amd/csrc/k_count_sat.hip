@@ -221,9 +221,14 @@ __global__ __launch_bounds__(256) void k_sat_tile(const uint64_t* __restrict__ b
     }
   }
 
-  // tile totals -> the row block's counters
+  // tile totals -> the row block's counters (each at most the tile's 4096
+  // pairs, so two share a 32-bit word through the wave sum)
 #pragma unroll
-  for (int k = 0; k < 6; ++k) cnt[k] = wave_sum_u32(cnt[k]);
+  for (int k = 0; k < 6; k += 2) {
+    const uint32_t t = wave_total_u32(cnt[k] | (cnt[k + 1] << 16));
+    cnt[k] = t & 0xFFFFu;
+    cnt[k + 1] = t >> 16;
+  }
   if (lane == 0)
 #pragma unroll
     for (int k = 0; k < 6; ++k) red[wave][k] = cnt[k];
