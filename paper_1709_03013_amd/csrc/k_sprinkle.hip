@@ -201,10 +201,14 @@ __global__ __launch_bounds__(256) void k_compact4d(
   }
 }
 
+// Lexicographic (k1, k2, idx), without branches: five 64-bit compares whose
+// lane masks combine with scalar logic, so a compare-exchange never splits
+// the wave.
 __device__ __forceinline__ bool rec_less(const SortRec& a, const SortRec& b) {
-  if (a.k1 != b.k1) return a.k1 < b.k1;
-  if (a.k2 != b.k2) return a.k2 < b.k2;
-  return a.idx < b.idx;
+  const bool lt1 = a.k1 < b.k1, eq1 = a.k1 == b.k1;
+  const bool lt2 = a.k2 < b.k2, eq2 = a.k2 == b.k2;
+  const bool lt3 = a.idx < b.idx;
+  return lt1 | (eq1 & (lt2 | (eq2 & lt3)));
 }
 
 // One record of lane ^ m of the wave.
@@ -216,9 +220,18 @@ __device__ __forceinline__ SortRec shfl_rec(const SortRec& r, int m) {
   return o;
 }
 
+// c ? b : a, field by field (selects, no branch).
+__device__ __forceinline__ SortRec sel(bool c, const SortRec& a, const SortRec& b) {
+  SortRec r;
+  r.k1 = c ? b.k1 : a.k1;
+  r.k2 = c ? b.k2 : a.k2;
+  r.idx = c ? b.idx : a.idx;
+  return r;
+}
+
 // The smaller (lo) or larger of a and b.
 __device__ __forceinline__ SortRec pick(const SortRec& a, const SortRec& b, bool lo) {
-  return rec_less(b, a) == lo ? b : a;
+  return sel(rec_less(b, a) == lo, a, b);
 }
 
 // Bitonic sort of n <= kSortTile records at base by 1024 threads, over the
@@ -246,11 +259,10 @@ __device__ __forceinline__ void tile_sort_body(SortRec* __restrict__ base, int64
     for (int j = k >> 1; j > 0; j >>= 1) {
       if (j == 1) {
         // positions p0 (lower) and p0 + 1
-        if (rec_less(r1, r0) == up) {
-          const SortRec x = r0;
-          r0 = r1;
-          r1 = x;
-        }
+        const bool sw = rec_less(r1, r0) == up;
+        const SortRec x = r0;
+        r0 = sel(sw, r0, r1);
+        r1 = sel(sw, r1, x);
       } else {
         const bool lo = ((p0 & j) == 0) == up;
         SortRec o0, o1;
