@@ -17,9 +17,12 @@ Two tiers, both written from the paper's definitions (arXiv:1709.03013):
   sprinkle uniform in w = tan(eta) and in angle, and its relation.
 * ``brute.py``: pure-Python brute force for tiny sets, used to pin the C code.
 
-Every function here has pins in ``tests/test_oracle_*.py``; the 4D action
-weights are the one reading the paper itself does not fix ("parity unpinned
-by the paper", pinned only by the chain/antichain closed forms).
+Every function here has pins in ``tests/test_oracle_*.py``.  The 4D action is
+a reading (the paper prints only the 2D one, Eq. 4): its weights and index
+convention are pinned by the identities Eq. 4's own weights satisfy in 2D
+(weights summing to 0, a chain giving N - 1, the vanishing squared-proper-time
+moment) and by hand-counted orders; its prefactor 4/sqrt(6) is "parity
+unpinned" (nothing in the paper fixes it).
 """
 from __future__ import annotations
 
