@@ -291,7 +291,8 @@ __device__ __forceinline__ void mfma_chunk(Acc (&acc)[Sh::TM][Sh::TN], uint32_t 
   const int lane = threadIdx.x & 63;
   const int r32 = lane & 31, g = lane >> 5;
   // dword q of the lane's 16 bytes holds columns cb + 32q .. cb + 32q + 31
-  // (labels and columns are below 2^24, so the differences fit an int)
+  // (a matrix that fits a device has fewer than 2^21 labels, so the
+  // differences fit an int)
   const int cb = (int)(256 * c) + 128 * g;
   if (mask_a) {
 #pragma unroll
