@@ -72,7 +72,7 @@ TRAFFIC = {
     "k_count_mfma_lds<int8>": {"bytes": 120657279934, "sources": "2d23d52a7de9b36f"},
     "k_count_pop": {"bytes": 2541574261038, "sources": "061d0d7fb6e6543a"},
     "k_sat_tile": {"bytes": 40522048602, "sources": "365513bf652c80e9"},
-    "k_link": {"bytes": 2585447480, "sources": "8e8c93b52090a515"},
+    "k_link": {"bytes": 2585447480, "sources": "21817441ebb6d6ec"},
 }
 KERNEL_SOURCES = {
     "k_count_mfma_lds<int8>": ["k_count_mfma.hip", "cs_device.h", "cs_internal.h"],
