@@ -76,7 +76,7 @@ def test_sprinkle_and_link_match_oracle(cs, ctx, d, N, seed):
 @pytest.mark.parametrize("d,N,seed", [(2, 2, 1), (2, 3, 2), (2, 64, 3), (2, 65, 4), (2, 200, 5),
                                       (2, 255, 16), (2, 256, 17), (2, 257, 18), (2, 1024, 1),
                                       (2, 1500, 12), (2, 2304, 19), (4, 64, 6), (4, 300, 7),
-                                      (4, 2048, 14), (4, 2500, 15), (4, 4097, 20)])
+                                      (4, 2048, 14), (4, 2500, 15), (2, 4096, 21), (4, 4097, 20)])
 def test_counts_match_oracle(cs, ctx, d, N, seed, path):
     say("case count d=%d N=%d seed=%d path=%d" % (d, N, seed, path))
     s = gpu_set(cs, ctx, d, N, seed)
