@@ -68,11 +68,11 @@ GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_reference.json")
 # after any change to them the figure no longer describes the kernel and is
 # reported as null.
 TRAFFIC = {
-    "k_count_mfma_lds<fp4>": {"bytes": 98463340503, "sources": "2d23d52a7de9b36f"},
-    "k_count_mfma_lds<int8>": {"bytes": 120657279934, "sources": "2d23d52a7de9b36f"},
-    "k_count_pop": {"bytes": 2541574261038, "sources": "061d0d7fb6e6543a"},
-    "k_sat_tile": {"bytes": 40522048602, "sources": "365513bf652c80e9"},
-    "k_link": {"bytes": 2585447480, "sources": "21817441ebb6d6ec"},
+    "k_count_mfma_lds<fp4>": {"bytes": 97438291327, "sources": "f707d13d54227e81"},
+    "k_count_mfma_lds<int8>": {"bytes": 120714210781, "sources": "f707d13d54227e81"},
+    "k_count_pop": {"bytes": 2552662941755, "sources": "061d0d7fb6e6543a"},
+    "k_sat_tile": {"bytes": 40521942564, "sources": "365513bf652c80e9"},
+    "k_link": {"bytes": 2587103209, "sources": "21817441ebb6d6ec"},
 }
 KERNEL_SOURCES = {
     "k_count_mfma_lds<int8>": ["k_count_mfma.hip", "cs_device.h", "cs_internal.h"],
