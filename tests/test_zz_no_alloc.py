@@ -26,7 +26,8 @@ def test_static_workspace_count_matches_caller_workspace():
     try:
         # the first call leaves 43-word rows in the array; the second, smaller
         # one must not see them
-        for d, N, seed, kmax, path in [(2, 9000, 5, 40, 3), (4, 3000, 6, 3, 2), (2, 700, 7, 3, 1)]:
+        for d, N, seed, kmax, path in [(2, 9000, 5, 40, 3), (4, 3000, 6, 3, 2), (2, 700, 7, 3, 1),
+                                       (2, 500, 8, 3, 3)]:
             say("case static workspace d=%d N=%d kmax=%d path=%d" % (d, N, kmax, path))
             s = cs.cs_sprinkle(ctx, d, N, seed)
             try:
